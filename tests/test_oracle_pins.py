@@ -1,0 +1,334 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks the oracle against a closed form the paper fixes (§2.1, Eq. 6:
+the impulse response b0*a1^(k-j)), a textbook/library routine (scipy's lfilter
+and upfirdn), brute force, or an invariant of the mathematics — chosen so that
+a dropped term, wrong sign, wrong index or transposed operand in the oracle
+fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.signal as sps
+
+import oracle
+from paper_1702_02256_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RTOL = 1e-12
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _bank(nf, rate=4096, seed=7, dmax=None, td=32, tu=32):
+    nf = np.asarray(nf, np.int32)
+    H = nf.shape[1]
+    dmax = dmax or W.multirate_dmax(rate, H)
+    b = W.random_bank(seed, nf, rate, dmax)
+    if H > 1:
+        b.h_down = W.down_taps(td)
+        b.h_up = W.up_taps(tu)
+    return b
+
+
+# ---------------------------------------------------------------- one filter
+
+
+@pytest.mark.parametrize("d,k0", [(0, 0), (5, 0), (3, 11), (17, 4)])
+def test_impulse_response_closed_form(d, k0):
+    """Eq. (6) with the delay of Eq. (7): y[k] = b0 a1^(k-k0-d) for k >= k0+d, else 0."""
+    rng = np.random.default_rng(1)
+    a = 0.97 * np.exp(1j * 2.1)
+    b = complex(rng.standard_normal(), rng.standard_normal())
+    n = 200
+    x = np.zeros(n)
+    x[k0] = 1.0
+    y = oracle.filter_one(a, b, d, x)
+    k = np.arange(n)
+    m = k - k0 - d
+    ref = np.where(m >= 0, b * a ** np.maximum(m, 0), 0.0)
+    assert _rel(y, ref) < RTOL
+
+
+def test_complex_exponential_closed_form():
+    """Geometric-series response to e^{i w k} from zero state (sum of Eq. 6)."""
+    a = 0.995 * np.exp(1j * 0.3)
+    b = 0.7 - 0.2j
+    d, w, n = 9, 0.71, 3000
+    k = np.arange(n)
+    x = np.exp(1j * w * k)
+    y = oracle.filter_one(a, b, d, x)
+    q = a * np.exp(-1j * w)
+    m = k - d
+    ref = np.where(m >= 0, b * np.exp(1j * w * m) * (1 - q ** (m + 1)) / (1 - q), 0)
+    assert _rel(y, ref) < 1e-11
+    # steady state: b e^{i w (k-d)} / (1 - a e^{-i w})
+    ss = b * np.exp(1j * w * (k - d)) / (1 - q)
+    assert np.max(np.abs(y[-100:] - ss[-100:])) / np.max(np.abs(ss)) < 1e-6
+
+
+def test_cosine_through_bank_path():
+    """Real input through the bank path: cos = (e^{+iwk} + e^{-iwk})/2."""
+    a = np.array([0.99 * np.exp(1j * 1.2), 0.95 * np.exp(-1j * 0.4)])
+    b = np.array([0.3 + 0.1j, -0.2 + 0.5j])
+    d = np.array([4, 0], np.int32)
+    tb = W.BankTables(4096, np.array([[2]], np.int32), a, b, d)
+    n, w = 1024, 0.37
+    k = np.arange(n)
+    z = oracle.run_stream(tb, np.cos(w * k))[0]
+    ref = np.zeros(n, complex)
+    for al, bl, dl in zip(a, b, d):
+        for s in (+1, -1):
+            q = al * np.exp(-1j * s * w)
+            m = k - dl
+            ref += 0.5 * np.where(m >= 0, bl * np.exp(1j * s * w * m) * (1 - q ** (m + 1)) / (1 - q), 0)
+    assert _rel(z, ref) < 1e-11
+
+
+# ---------------------------------------------------------------- single-rate banks
+
+
+def _lfilter_bank(tb, x):
+    """Per filter: scipy lfilter([b0], [1, -a1]) on the delayed input; summed per template."""
+    off = tb.offsets()
+    T = tb.n_templates
+    n = len(x)
+    z = np.zeros((T, n), complex)
+    for t in range(T):
+        for l in range(tb.n_filters[t, 0]):
+            f = off[t, 0] + l
+            xd = np.concatenate([np.zeros(tb.delay[f]), x])[:n]
+            z[t] += sps.lfilter([tb.b0[f]], [1.0, -tb.a1[f]], xd.astype(complex))
+    return z
+
+
+def test_bank_matches_lfilter():
+    tb = _bank([[5], [3], [8]], rate=512, dmax=[40])
+    x = np.random.default_rng(3).standard_normal(700)
+    assert _rel(oracle.run_stream(tb, x), _lfilter_bank(tb, x)) < 1e-12
+
+
+def test_bank_matches_bruteforce_convolution():
+    """z[k] = sum_l sum_{m=0}^{k-d_l} b0_l a1_l^m x[k-d_l-m] (finite stream, zero state)."""
+    tb = _bank([[4], [2]], rate=64, dmax=[6])
+    n = 40
+    x = np.random.default_rng(4).standard_normal(n)
+    off = tb.offsets()
+    ref = np.zeros((2, n), complex)
+    for t in range(2):
+        for l in range(tb.n_filters[t, 0]):
+            f = off[t, 0] + l
+            a, b, d = tb.a1[f], tb.b0[f], int(tb.delay[f])
+            for k in range(n):
+                for m in range(0, k - d + 1):
+                    ref[t, k] += b * a ** m * x[k - d - m]
+    assert _rel(oracle.run_stream(tb, x), ref) < 1e-12
+
+
+def test_linearity():
+    tb = _bank([[6], [9]], rate=256, dmax=[30])
+    rng = np.random.default_rng(5)
+    x1, x2 = rng.standard_normal(300), rng.standard_normal(300)
+    z = oracle.run_stream(tb, 2.5 * x1 - 0.75 * x2)
+    ref = 2.5 * oracle.run_stream(tb, x1) - 0.75 * oracle.run_stream(tb, x2)
+    assert _rel(z, ref) < 1e-12
+
+
+def test_time_shift():
+    """Delaying the input by s samples delays the output by s samples."""
+    tb = _bank([[7]], rate=256, dmax=[20])
+    x = np.random.default_rng(6).standard_normal(256)
+    s = 32
+    z = oracle.run_stream(tb, x)
+    zs = oracle.run_stream(tb, np.concatenate([np.zeros(s), x[:-s]]))
+    assert _rel(zs[:, s:], z[:, :-s]) < 1e-12
+    assert np.all(zs[:, :s] == 0)
+
+
+def test_permutation_and_zero_padding_invariance():
+    """Filter order does not matter; zero-coefficient filters add nothing (the
+    paper pads banks with zero filters to powers of two, §5, Table 5)."""
+    tb = _bank([[9]], rate=256, dmax=[50])
+    x = np.random.default_rng(8).standard_normal(400)
+    z = oracle.run_stream(tb, x)
+    p = np.random.default_rng(9).permutation(9)
+    tp = W.BankTables(256, tb.n_filters.copy(), tb.a1[p], tb.b0[p], tb.delay[p])
+    assert _rel(oracle.run_stream(tp, x), z) < 1e-13
+    pad = 7
+    tz = W.BankTables(256, np.array([[9 + pad]], np.int32),
+                      np.concatenate([tb.a1, np.zeros(pad)]),
+                      np.concatenate([tb.b0, np.zeros(pad)]),
+                      np.concatenate([tb.delay, np.arange(pad, dtype=np.int32)]))
+    assert np.array_equal(oracle.run_stream(tz, x), z)
+
+
+# ---------------------------------------------------------------- resampling
+
+
+def test_downsample_matches_upfirdn():
+    h = W.down_taps(32)
+    x = np.random.default_rng(10).standard_normal(512)
+    ref = sps.upfirdn(h, x, up=1, down=2)[: len(x) // 2]
+    assert _rel(oracle.downsample(h, x), ref) < 1e-13
+
+
+def test_upsample_add_matches_upfirdn():
+    h = W.up_taps(32)
+    rng = np.random.default_rng(11)
+    low = rng.standard_normal(128) + 1j * rng.standard_normal(128)
+    z = rng.standard_normal(256) + 1j * rng.standard_normal(256)
+    ref = z + sps.upfirdn(h, low, up=2, down=1)[:256]
+    assert _rel(oracle.upsample_add(h, low, z), ref) < 1e-13
+
+
+def _scipy_multirate(tb, x):
+    """The whole multi-rate scheme rebuilt from scipy routines."""
+    H, T, n = tb.n_bands, tb.n_templates, len(x)
+    xs = [np.asarray(x, float)]
+    for h in range(1, H):
+        xs.append(sps.upfirdn(tb.h_down, xs[-1], 1, 2)[: n >> h])
+    off = tb.offsets()
+    z = np.zeros((T, n), complex)
+    for t in range(T):
+        zb = []
+        for h in range(H):
+            nh = n >> h
+            acc = np.zeros(nh, complex)
+            for l in range(tb.n_filters[t, h]):
+                f = off[t, h] + l
+                xd = np.concatenate([np.zeros(tb.delay[f]), xs[h]])[:nh]
+                acc += sps.lfilter([tb.b0[f]], [1.0, -tb.a1[f]], xd.astype(complex))
+            zb.append(acc)
+        acc = zb[H - 1]
+        for h in range(H - 2, -1, -1):
+            acc = zb[h] + sps.upfirdn(tb.h_up, acc, 2, 1)[: n >> h]
+        z[t] = acc
+    return z
+
+
+@pytest.mark.parametrize("nf", [[[0, 5]], [[3, 4, 2]], [[2, 0, 3, 1], [0, 0, 0, 4]]])
+def test_multirate_matches_scipy_composition(nf):
+    tb = _bank(nf, rate=1024, seed=12)
+    n = 512
+    x = np.random.default_rng(13).standard_normal(n)
+    assert _rel(oracle.run_stream(tb, x), _scipy_multirate(tb, x)) < 1e-11
+
+
+def test_pure_delay_taps_reduce_to_decimation_and_zero_stuffing():
+    """h_d = h_u = delta: x_1[m] = x[2m]; acc_0[k] = z_0[k] + (k even) acc_1[k/2]."""
+    tb = _bank([[3, 2]], rate=256, seed=14)
+    tb.h_down = np.array([1.0])
+    tb.h_up = np.array([1.0])
+    n = 200
+    x = np.random.default_rng(15).standard_normal(n)
+    z = oracle.run_stream(tb, x)[0]
+    t0 = tb.subset([0])
+    single0 = W.BankTables(256, np.array([[3]], np.int32), t0.a1[:3], t0.b0[:3], t0.delay[:3])
+    single1 = W.BankTables(128, np.array([[2]], np.int32), t0.a1[3:], t0.b0[3:], t0.delay[3:])
+    z0 = _lfilter_bank(single0, x)[0]
+    z1 = _lfilter_bank(single1, x[0::2])[0]
+    ref = z0.copy()
+    ref[0::2] += z1
+    assert _rel(z, ref) < 1e-12
+
+
+def test_single_band_equals_single_rate():
+    tb = _bank([[6]], rate=512, dmax=[25])
+    x = np.random.default_rng(16).standard_normal(333)
+    assert _rel(oracle.run_stream(tb, x), _lfilter_bank(tb, x)) < 1e-12
+
+
+def test_band_with_no_filters_still_carries_the_chain():
+    tb = _bank([[4, 0, 3]], rate=512, seed=17)
+    x = np.random.default_rng(18).standard_normal(256)
+    assert _rel(oracle.run_stream(tb, x), _scipy_multirate(tb, x)) < 1e-11
+
+
+# ---------------------------------------------------------------- streaming
+
+
+@pytest.mark.parametrize("block", [4, 8, 64, 200])
+def test_block_split_invariance(block):
+    tb = _bank([[5, 3, 4], [2, 6, 1]], rate=1024, seed=19)
+    n = 800
+    x = np.random.default_rng(20).standard_normal(n)
+    whole = oracle.run_stream(tb, x)
+    bank = oracle.OracleBank(tb)
+    parts, i = [], 0
+    sizes = [block, 2 * block, block // 2 if block >= 8 else block]
+    j = 0
+    while i < n:
+        s = min(sizes[j % len(sizes)], n - i)
+        parts.append(bank.process(x[i:i + s]))
+        i += s
+        j += 1
+    assert _rel(np.concatenate(parts, axis=1), whole) < 1e-13
+    assert bank.samples_done == n
+
+
+def test_rejects_block_not_multiple_of_lowest_rate():
+    tb = _bank([[2, 2, 2]], rate=512)
+    bank = oracle.OracleBank(tb)
+    with pytest.raises(ValueError):
+        bank.process(np.zeros(6))
+
+
+# ---------------------------------------------------------------- inputs and accounting
+
+
+def test_tap_design_matches_firwin():
+    for ntaps, att in [(32, 60.0), (384, 100.0)]:
+        beta = W.kaiser_beta(att)
+        ref = sps.firwin(ntaps, 0.5, window=("kaiser", beta))
+        h = W.kaiser_lowpass(ntaps, 0.5, att)
+        assert np.allclose(h, ref / ref.sum(), rtol=0, atol=1e-14)
+    assert abs(W.kaiser_beta(60.0) - 5.6533) < 1e-3
+    assert abs(W.down_taps(32).sum() - 1.0) < 1e-14
+    hu = W.up_taps(32)
+    assert abs(hu[0::2].sum() - 1.0) < 1e-14 and abs(hu[1::2].sum() - 1.0) < 1e-14
+
+
+def test_dc_gain_through_the_chain():
+    """A constant input reaches every band with gain 1 and an all-pass chain
+    returns it at the base rate with gain 1 (tap normalisation rules)."""
+    n = 1024
+    x = np.ones(n)
+    h = W.down_taps(32)
+    d = oracle.downsample(h, x)
+    assert np.allclose(d[40:], 1.0, atol=1e-12)
+    low = np.ones(256, complex)
+    acc = oracle.upsample_add(W.up_taps(32), low, np.zeros(512, complex))
+    assert np.allclose(acc[40:], 1.0, atol=1e-12)
+
+
+def test_cost_model_matches_paper_table():
+    """12 flops per filter-sample (§2.2) reproduces the relative CPU filtering
+    times of Table 3 within 3% when 1024 filters are split equally over rates."""
+    g = json.load(open(os.path.join(HERE, "golden", "multirate_cost.json")))
+    base = None
+    for r, cpu in zip(g["n_rates"], g["cpu_spiir_filtering_s"]):
+        m = g["total_filters"] // r
+        nf = np.array([[m] * r], np.int32)
+        tb = W.BankTables(g["base_rate_hz"], nf, np.zeros(m * r, complex), np.zeros(m * r, complex),
+                          np.zeros(m * r, np.int32))
+        flops = W.algorithmic_flops(tb, g["base_rate_hz"])["filter"]
+        if base is None:
+            base, cpu0 = flops, cpu
+            assert flops == 12 * 1024 * 4096
+        assert abs((flops / base) / (cpu / cpu0) - 1.0) < 0.03
+
+
+def test_generators_are_subset_consistent():
+    full = W.config3(n_templates=6, n_blocks=1)
+    part = W.config3(n_templates=6, n_blocks=1, templates=[4, 1])
+    ref = full.bank.subset([4, 1])
+    assert np.array_equal(part.bank.n_filters, ref.n_filters)
+    assert np.array_equal(part.bank.a1, ref.a1) and np.array_equal(part.bank.delay, ref.delay)
+    c = W.uneven_counts(1, 200)
+    assert np.all(c[:, 0] >= 1) and np.all((c > 0).sum(1) >= 1) and np.all((c > 0).sum(1) <= 7)
+    assert c.sum(1).min() >= 1 and c.sum(1).max() <= 1024
