@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput of multi-rate SPIIR filtering on one MI355X.
+
+A step is one block of the whole hot path (input staging and downsample
+cascade, filter bank with carry correction and filter sum, upsample-and-add,
+output write) for every template of the bank, with the state carried from the
+previous block.  The default workload is the multi-rate bank: 4096 templates
+over 7 bands (4096..64 Hz), 40..300 filters per band, 32-tap resampling, 1 s
+blocks.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0
+METRIC = "template-filter-samples/s + real-time templates/GPU; p99 block latency"
+
+
+def make_workload(cfg: int, templates: int | None, steps: int):
+    from paper_1702_02256_amd import workloads as W
+    nb = max(steps, 1)
+    if cfg == 1:
+        return W.config1()
+    if cfg == 2:
+        return W.config2(n_templates=templates or 1024, n_blocks=nb)
+    if cfg == 3:
+        return W.config3(n_templates=templates or 4096, n_blocks=nb)
+    if cfg == 4:
+        return W.config4(n_templates=templates or 8192, n_blocks=nb)
+    raise SystemExit(f"unknown config {cfg}")
+
+
+def cpu_baseline(wl, block: int, budget_s: float):
+    """The FP64 oracle on a bounded sample of the same workload, timed on the host."""
+    import numpy as np
+
+    import oracle
+    T = wl.bank.n_templates
+    ns = min(T, 512)
+    sel = np.unique(np.linspace(0, T - 1, ns).round().astype(np.int64))
+    sub = wl.bank.subset(sel)
+    x = wl.stream()
+    bank = oracle.OracleBank(sub)
+    fs_block = sub.filter_samples_per_block(block)
+    done, fs = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        if (done + 1) * block > len(x):
+            break
+        bank.process(x[done * block:(done + 1) * block])
+        done += 1
+        fs += fs_block
+        if time.perf_counter() - t0 >= budget_s and done >= 2:
+            break
+    dt = time.perf_counter() - t0
+    bank.close()
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {
+        "value": fs / dt,
+        "unit": "template-filter-samples/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{len(sel)} of {T} templates (evenly spaced), {done} blocks of {block} "
+                  f"samples, FP64 C oracle (gcc -O2, OpenMP over templates), {dt:.2f} s wall",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4])
+    ap.add_argument("--templates", type=int, default=None)
+    ap.add_argument("--filters-per-lane", type=int, default=0)
+    ap.add_argument("--waves-per-group", type=int, default=0)
+    ap.add_argument("--carry-chunk", type=int, default=0)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_compensated"])
+    ap.add_argument("--cpu-budget", type=float, default=2.0,
+                    help="wall seconds of oracle work for the CPU baseline (0 = skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(templates shard across GPUs with no exchange; run one process per GPU "
+              "on its own bank instead)", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1702_02256_amd import spiir as S
+    from paper_1702_02256_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    K, Wm = args.steps, args.warmup
+    wl = make_workload(args.config, args.templates, K + Wm)
+    tb = wl.bank
+    block = wl.block
+    T = tb.n_templates
+    x = wl.stream() if args.config != 1 else np.tile(wl.stream(), K + Wm)
+    n_blocks_avail = len(x) // block
+    xt = torch.from_numpy(x[: n_blocks_avail * block].astype(np.float32)).cuda()
+
+    stream = torch.cuda.Stream()
+    bank = S.Bank(tb, block, stream=stream, precision=args.precision,
+                  carry_chunk=args.carry_chunk, filters_per_lane=args.filters_per_lane,
+                  waves_per_group=args.waves_per_group)
+    z = torch.zeros((T, block), dtype=torch.complex64, device="cuda")
+    fs_block = tb.filter_samples_per_block(block)
+    flops = W.algorithmic_flops(tb, block)
+
+    def blk(i):
+        j = i % n_blocks_avail
+        return xt[j * block:(j + 1) * block]
+
+    with torch.cuda.stream(stream):
+        for i in range(Wm):
+            bank.process_block(blk(i), z, stream)
+        torch.cuda.synchronize()
+        S.spiir_profile_enable(True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        t0 = time.perf_counter()
+        evs[0].record(stream)
+        for i in range(K):
+            bank.process_block(blk(Wm + i), z, stream)
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    prof = S.spiir_profile_read()
+    S.spiir_profile_enable(False)
+    rc, _ = bank.status()
+    if rc != 0:
+        raise SystemExit(f"bank status: {S.spiir_strerror(rc)}")
+    plan = bank.plan
+    bank.destroy()
+
+    wall = t1 - t0
+    lat = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(K)])
+    value = fs_block * K / wall
+    block_s = block / tb.base_rate
+    ms_step = wall / K * 1e3
+    filt_ms = prof["filter"]["ms"] / max(prof["filter"]["launches"], 1)
+    filt_launch_per_step = prof["filter"]["launches"] / K
+    flops_per_launch = flops["filter"] / filt_launch_per_step
+    achieved = flops_per_launch / (filt_ms * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "template-filter-samples/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "templates": T,
+            "bands": tb.n_bands,
+            "base_rate_hz": tb.base_rate,
+            "block_samples": block,
+            "filters": tb.total_filters,
+            "filter_samples_per_block": fs_block,
+            "precision": args.precision,
+            "filters_per_lane": plan["filters_per_lane"],
+            "lanes_per_group": plan["lanes_per_group"],
+            "carry_chunk": plan["carry_chunk"],
+        },
+        "real_time_templates": T * block_s / (ms_step * 1e-3),
+        "block_latency_ms": {"p50": float(np.percentile(lat, 50)),
+                             "p99": float(np.percentile(lat, 99)),
+                             "kind": "closed loop, back-to-back blocks (GPU time per block)"},
+        "fp32_peak_fraction_whole_step": flops["total"] / (ms_step * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+        "kernel_ms_per_step": {k: v["ms"] / K for k, v in prof.items()},
+        "roofline": {
+            "kernel": "k_filter (filter bank: Eq. 7 recurrence, carry correction, Eq. 8 sum)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "algorithmic_flops_per_launch": flops_per_launch,
+            "avg_launch_ms": filt_ms,
+        },
+    }
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, block, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * spiir.h — C ABI of the MI355X SPIIR filtering library (libspiir.so).
+ *
+ * The library runs Summed Parallel IIR (SPIIR) filtering, single-rate and
+ * multi-rate, on one AMD Instinct MI355X (gfx950) with hand-written HIP kernels.
+ * It follows Guo et al., "Acceleration of low-latency gravitational wave
+ * searches using Maxwell-microarchitecture GPUs":
+ *
+ *   §2.1, Eq. (7):  every filter l of a template runs the delayed first-order
+ *                   complex recurrence  y_l[k] = a1_l y_l[k-1] + b0_l x[k - d_l];
+ *   §2.1, Eq. (8):  the template output is the sum over its filters,
+ *                   z[k] = sum_l y_l[k]  (the 2*dt factor of Eq. 8 is not
+ *                   applied: fold any scale into b0; the map is linear);
+ *   §2.2 (Fig. "multi"): the input is halved in rate band by band with a
+ *                   low-pass FIR (Eq. 9 describes the resampling filter), each
+ *                   band is filtered with its own filters, and the lowest
+ *                   band's output is upsampled by 2 and added to the next
+ *                   band's output, up to the input rate.
+ *
+ * Conventions that the paper leaves open and this library fixes:
+ *   - zero filter state and zero input before the stream starts;
+ *   - delays d are integer samples at the band's own rate (d = 0: current);
+ *   - downsampling: x_h[m] = sum_{j<T_d} h_down[j] x_{h-1}[2m - j] (causal,
+ *     keeps even absolute indices, no group-delay compensation);
+ *   - upsample-and-add: acc_h[k] = z_h[k] + sum_{j<T_u} h_up[j] v[k - j], where
+ *     v[2m] = acc_{h+1}[m] and v[odd] = 0; acc_{H-1} = z_{H-1}; output acc_0.
+ *
+ * Threading: a bank must not be used by two host threads at once; different
+ * banks may be.  No call throws; every call returns a status code.
+ * Memory: all device memory a bank needs is allocated by spiir_create and freed
+ * by spiir_destroy; the processing calls allocate nothing.
+ */
+#ifndef SPIIR_H
+#define SPIIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Interleaved complex64 output sample. */
+typedef struct {
+    float re;
+    float im;
+} spiir_c32;
+
+typedef struct spiir_bank spiir_bank;
+
+/* Status codes (0 = success, negative = error). */
+enum {
+    SPIIR_OK = 0,
+    SPIIR_EINVAL = -1,     /* bad argument; nothing was enqueued, state unchanged   */
+    SPIIR_ENOMEM = -2,     /* device allocation failed or over the stated budget    */
+    SPIIR_EDEVICE = -3,    /* HIP error; the bank is poisoned and must be destroyed */
+    SPIIR_EORDER = -4,     /* request order/aliasing violated (e.g. a bank twice)   */
+    SPIIR_ENONFINITE = -5  /* a template's state or output became non-finite        */
+};
+
+/* Arithmetic of the filter sum. */
+enum {
+    SPIIR_FP32 = 0,             /* complex FP32, plain summation over filters      */
+    SPIIR_FP32_COMPENSATED = 1  /* complex FP32, error-free (TwoSum) cross-lane sum */
+};
+
+/*
+ * Bank descriptor (read only during the call that receives it; the caller
+ * keeps ownership of every array).
+ *
+ *   n_templates, n_bands  T >= 1 templates, H in [1, 12] bands; band h runs at
+ *                         base_rate_hz / 2^h.
+ *   n_filters             [T*H] filters of template t at band h, index t*H + h;
+ *                         0 = band inactive for that template.
+ *   a1, b0                complex128 interleaved (re, im), one pair per filter,
+ *                         concatenated in (template, band, filter) order; |a1|
+ *                         must be < 1 for a stable filter (not enforced), all
+ *                         values finite.
+ *   delay                 one int32 per filter, in [0, SPIIR_MAX_DELAY], in
+ *                         samples at the band's rate.
+ *   n_taps_down, h_down   T_d real taps of the /2 anti-alias FIR (H > 1).
+ *   n_taps_up, h_up       T_u real taps of the x2 interpolation FIR (H > 1).
+ *   max_block             largest block, in base-rate samples, that
+ *                         process calls will pass; a multiple of 2^(H-1).
+ *   precision             SPIIR_FP32 or SPIIR_FP32_COMPENSATED.
+ *   carry_chunk           C: every C samples (absolute band index) the FP32
+ *                         state is corrected by (a1^C - fl32(a1)^C) times the
+ *                         state at the chunk start, computed in FP64 at
+ *                         create; a multiple of 16 in [16, 1024]; 0 = 32.
+ *   filters_per_lane      F in {1, 2, 4, 8}; 0 = library default.
+ *   waves_per_group       wave64s per workgroup in [1, 16] ([1, 8] when
+ *                         filters_per_lane is 8); 0 = default.
+ *   device                HIP device ordinal the bank lives on.
+ */
+typedef struct {
+    int32_t n_templates;
+    int32_t n_bands;
+    int32_t base_rate_hz;
+    const int32_t* n_filters;
+    const double* a1;
+    const double* b0;
+    const int32_t* delay;
+    int32_t n_taps_down;
+    const double* h_down;
+    int32_t n_taps_up;
+    const double* h_up;
+    int32_t max_block;
+    int32_t precision;
+    int32_t carry_chunk;
+    int32_t filters_per_lane;
+    int32_t waves_per_group;
+    int32_t device;
+} spiir_bank_desc;
+
+#define SPIIR_MAX_BANDS 12
+#define SPIIR_MAX_DELAY 16383
+#define SPIIR_MAX_TAPS 1024
+#define SPIIR_MAX_BATCH 16
+
+/* One request of a batch: the next n samples of the stream bound to `bank`. */
+typedef struct {
+    spiir_bank* bank;
+    const float* x_dev;
+    int64_t n;
+    spiir_c32* z_dev;
+    int64_t ldz;
+} spiir_request;
+
+/*
+ * spiir_footprint — device bytes spiir_create would allocate for `desc`.
+ * Pure host function: no device call, no allocation.  Returns SPIIR_EINVAL for
+ * a descriptor spiir_create would reject.  Used for admission by HBM footprint.
+ */
+int spiir_footprint(const spiir_bank_desc* desc, size_t* bytes);
+
+/*
+ * spiir_create — validate, plan and upload a bank.
+ * Copies the tables (converted to FP32 in the library's lane order), computes
+ * the FP64 carry corrections on the device, and allocates state, input
+ * histories, workspace and per-template up-chain histories.  `hip_stream`
+ * (hipStream_t or NULL for the null stream) orders the uploads.  On success
+ * *out owns all device memory; on error *out is NULL and the return is
+ * SPIIR_EINVAL, SPIIR_ENOMEM or SPIIR_EDEVICE.  One bank is bound to one input
+ * stream (its histories carry that stream).
+ */
+int spiir_create(const spiir_bank_desc* desc, void* hip_stream, spiir_bank** out);
+
+/*
+ * spiir_process_block — filter the next n samples of the bank's stream
+ * (Eqs. 7-8, and the §2.2 chain when H > 1).
+ *   x_dev  device pointer, n FP32 samples at the base rate (caller-owned).
+ *   n      0 < n <= max_block and n % 2^(H-1) == 0, else SPIIR_EINVAL with
+ *          nothing enqueued and the state unchanged.
+ *   z_dev  device pointer, complex64, row t at z_dev + t*ldz, n samples:
+ *          z_dev[t*ldz + k] is the output for absolute sample
+ *          (samples_done + k).  ldz >= n.
+ * Asynchronous on `hip_stream`; the stream first waits for the bank's previous
+ * work, so per-bank order holds across streams.  Buffers must stay valid until
+ * the work completes.  Allocates nothing.
+ */
+int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
+                        int64_t ldz, void* hip_stream);
+
+/*
+ * spiir_process_batch — one launch sequence over up to SPIIR_MAX_BATCH
+ * requests of different banks (each bank at most once: SPIIR_EORDER
+ * otherwise; concatenate consecutive blocks of one stream instead).  Banks in
+ * one batch must share device, filters_per_lane, waves_per_group and
+ * precision (SPIIR_EINVAL otherwise).  Every result equals what separate
+ * spiir_process_block calls give, bit for bit.  Validation is all-or-nothing.
+ */
+int spiir_process_batch(int32_t n_req, const spiir_request* req, void* hip_stream);
+
+/* spiir_reset — zero every state (filters, histories, flags, sample count).
+ * Synchronous. */
+int spiir_reset(spiir_bank* bank);
+
+/* spiir_state_size — bytes of the blob spiir_save_state writes. */
+int spiir_state_size(const spiir_bank* bank, size_t* bytes);
+
+/* spiir_save_state — copy the carried state (filter states, chunk-start
+ * states, input histories, up-chain histories, flags, sample count) into
+ * host_buf (spiir_state_size bytes).  Waits for the bank's work. */
+int spiir_save_state(spiir_bank* bank, void* host_buf, void* hip_stream);
+
+/* spiir_load_state — restore a blob from spiir_save_state of a bank with the
+ * same shape (SPIIR_EINVAL if the header does not match).  Synchronous. */
+int spiir_load_state(spiir_bank* bank, const void* host_buf, void* hip_stream);
+
+/* spiir_status — sticky non-finite flags.  Waits for the bank's work.
+ * template_flags (may be NULL): host array of n_templates, set to 1 where the
+ * template's state went non-finite.  Returns SPIIR_ENONFINITE if any is set,
+ * SPIIR_EDEVICE if the bank is poisoned, else SPIIR_OK.  spiir_reset clears. */
+int spiir_status(spiir_bank* bank, int32_t* template_flags);
+
+/* spiir_destroy — wait for the bank's outstanding work, then free it.
+ * NULL is accepted. */
+int spiir_destroy(spiir_bank* bank);
+
+/* spiir_strerror — static description of a status code. */
+const char* spiir_strerror(int status);
+
+/* ---- introspection (no effect on results) ---------------------------- */
+
+/* Samples consumed so far, at the base rate. */
+int spiir_samples_done(const spiir_bank* bank, int64_t* samples);
+
+/* Plan summary for a descriptor, computed on the host without a device. */
+typedef struct {
+    int64_t total_filters;    /* sum of n_filters                              */
+    int64_t filter_slots;     /* lanes x F over all workgroups (incl. padding) */
+    int32_t n_groups;         /* workgroups of the filter kernel               */
+    int32_t n_pieces;         /* (template, band) pieces after splitting       */
+    int32_t lanes_per_group;  /* 64 x waves_per_group                          */
+    int32_t filters_per_lane; /* F                                             */
+    int32_t lds_bytes;        /* dynamic LDS of the filter kernel              */
+    int32_t carry_chunk;      /* C                                             */
+    size_t footprint;         /* device bytes spiir_create allocates           */
+} spiir_plan_info;
+
+int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info);
+
+/* Process-wide kernel timing with HIP events recorded around each kernel the
+ * library launches.  spiir_profile_enable(1) clears and starts recording;
+ * spiir_profile_read waits for the recorded events and returns, per kernel
+ * kind (0 = input staging and downsample cascade, 1 = filter bank, 2 =
+ * upsample-and-add / output), the launch count and total milliseconds. */
+typedef struct {
+    int64_t launches[3];
+    double ms[3];
+} spiir_profile_data;
+
+int spiir_profile_enable(int enable);
+int spiir_profile_read(spiir_profile_data* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIIR_H */

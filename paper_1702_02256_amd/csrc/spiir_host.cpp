@@ -1,0 +1,866 @@
+// Host side of the SPIIR library: descriptor validation, the lane/workgroup
+// planner, device memory, launch sequencing, state and status.  Exposes the C
+// ABI declared in include/spiir.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "spiir.h"
+#include "spiir_internal.h"
+
+using namespace spiir;
+
+namespace {
+
+constexpr int kDefaultF = 4;
+constexpr int kDefaultW = 4;
+constexpr int kDefaultC = 32;
+constexpr int kInner = 4096;        // base-rate samples per launch sequence
+constexpr int kXcapDefault = 8192;  // LDS window, floats
+constexpr int kXcapMax = 24576;
+constexpr int kXcapSlack = 512;     // window samples beyond the largest delay
+constexpr int kMaxLds = 160 * 1024;
+constexpr uint32_t kStateMagic = 0x53504952u;  // "SPIR"
+constexpr uint32_t kStateVersion = 1;
+
+int64_t next_pow2(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+struct Plan {
+    int T = 0, H = 0, L = 0, F = 0, W = 0, C = 0, precision = 0;
+    int td = 0, tu = 0, hu_len = 0, max_block = 0, mb_inner = 0;
+    int xcap = 0;
+    int nrun_max = 1, npiece_max = 1;
+    int lds_filter = 0, lds_stage = 0, lds_up = 0;
+    int64_t total_filters = 0, n_slots = 0, zw_elems = 0, ring_total = 0;
+    std::vector<int> maxd_band, S, ring_mask;
+    std::vector<int64_t> ring_off;
+    std::vector<int> band_wg0;
+    std::vector<WgDesc> wg;
+    std::vector<PieceDesc> piece;
+    std::vector<SegDesc> seg;
+    std::vector<int32_t> lane_meta;
+    std::vector<int64_t> slot_src;  // desc filter index, -1 = padding
+    std::vector<int32_t> slot_off;
+    size_t footprint = 0;
+};
+
+bool finite_all(const double* p, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+int validate(const spiir_bank_desc* d)
+{
+    if (!d) return SPIIR_EINVAL;
+    if (d->n_templates < 1 || d->n_bands < 1 || d->n_bands > SPIIR_MAX_BANDS) return SPIIR_EINVAL;
+    if (d->base_rate_hz <= 0 || !d->n_filters) return SPIIR_EINVAL;
+    const int H = d->n_bands;
+    if (d->max_block <= 0 || d->max_block > (1 << 26)) return SPIIR_EINVAL;
+    if (d->max_block % (1 << (H - 1)) != 0) return SPIIR_EINVAL;
+    if (d->precision != SPIIR_FP32 && d->precision != SPIIR_FP32_COMPENSATED) return SPIIR_EINVAL;
+    const int C = d->carry_chunk ? d->carry_chunk : kDefaultC;
+    if (C < 16 || C > 1024 || (C & (C - 1)) != 0) return SPIIR_EINVAL;
+    const int F = d->filters_per_lane ? d->filters_per_lane : kDefaultF;
+    if (F != 1 && F != 2 && F != 4 && F != 8) return SPIIR_EINVAL;
+    const int W = d->waves_per_group ? d->waves_per_group : kDefaultW;
+    if (W < 1 || 64 * W > filter_max_threads(F)) return SPIIR_EINVAL;
+    if (d->device < 0) return SPIIR_EINVAL;
+    int64_t total = 0;
+    for (int64_t s = 0; s < (int64_t)d->n_templates * H; ++s) {
+        if (d->n_filters[s] < 0) return SPIIR_EINVAL;
+        total += d->n_filters[s];
+    }
+    if (total > 0) {
+        if (!d->a1 || !d->b0 || !d->delay) return SPIIR_EINVAL;
+        if (!finite_all(d->a1, 2 * total) || !finite_all(d->b0, 2 * total)) return SPIIR_EINVAL;
+        for (int64_t l = 0; l < total; ++l)
+            if (d->delay[l] < 0 || d->delay[l] > SPIIR_MAX_DELAY) return SPIIR_EINVAL;
+    }
+    if (H > 1) {
+        if (d->n_taps_down < 1 || d->n_taps_down > SPIIR_MAX_TAPS || !d->h_down) return SPIIR_EINVAL;
+        if (d->n_taps_up < 1 || d->n_taps_up > SPIIR_MAX_TAPS || !d->h_up) return SPIIR_EINVAL;
+        if (!finite_all(d->h_down, d->n_taps_down) || !finite_all(d->h_up, d->n_taps_up))
+            return SPIIR_EINVAL;
+    }
+    return SPIIR_OK;
+}
+
+// Lays out the bank: segments of each band end to end in lane space, cut into
+// workgroups of L lanes; a segment crossing a workgroup boundary becomes two
+// pieces.  Padding lanes and slots carry zero coefficients (their outputs are
+// exactly zero) and belong to the last piece of their workgroup.
+int make_plan(const spiir_bank_desc* d, Plan& p)
+{
+    int rc = validate(d);
+    if (rc) return rc;
+    p = Plan();
+    p.T = d->n_templates;
+    p.H = d->n_bands;
+    p.F = d->filters_per_lane ? d->filters_per_lane : kDefaultF;
+    p.W = d->waves_per_group ? d->waves_per_group : kDefaultW;
+    p.L = 64 * p.W;
+    p.C = d->carry_chunk ? d->carry_chunk : kDefaultC;
+    p.precision = d->precision;
+    p.max_block = d->max_block;
+    p.mb_inner = std::min(d->max_block, kInner);
+    p.td = p.H > 1 ? d->n_taps_down : 1;
+    p.tu = p.H > 1 ? d->n_taps_up : 1;
+    p.hu_len = (p.tu + 1) / 2;
+    const int T = p.T, H = p.H, L = p.L, F = p.F;
+
+    std::vector<int64_t> moff((size_t)T * H);
+    int64_t total = 0;
+    for (int64_t s = 0; s < (int64_t)T * H; ++s) {
+        moff[s] = total;
+        total += d->n_filters[s];
+    }
+    p.total_filters = total;
+
+    p.maxd_band.assign(H, 0);
+    for (int t = 0; t < T; ++t)
+        for (int h = 0; h < H; ++h)
+            for (int l = 0; l < d->n_filters[t * H + h]; ++l)
+                p.maxd_band[h] = std::max(p.maxd_band[h], (int)d->delay[moff[t * H + h] + l]);
+
+    // LDS window: maxd + S floats, S a multiple of kTile (or the whole band block)
+    int X = kXcapDefault;
+    for (int h = 0; h < H; ++h)
+        X = std::max(X, p.maxd_band[h] + std::min(kXcapSlack, p.mb_inner >> h) + kTile);
+    X = (X + 3) & ~3;
+    if (X > kXcapMax) return SPIIR_EINVAL;
+    p.xcap = X;
+    p.S.assign(H, 0);
+    p.ring_mask.assign(H, 0);
+    p.ring_off.assign(H, 0);
+    for (int h = 0; h < H; ++h) {
+        const int nh = p.mb_inner >> h;
+        const int room = ((X - p.maxd_band[h]) / kTile) * kTile;
+        p.S[h] = std::max(1, std::min(nh, room));
+        const int64_t P = next_pow2((int64_t)nh + std::max(p.maxd_band[h], p.td) + 1);
+        p.ring_mask[h] = (int)(P - 1);
+        p.ring_off[h] = p.ring_total;
+        p.ring_total += P;
+    }
+
+    p.seg.assign((size_t)T * H, SegDesc{0, 0, 0});
+    p.band_wg0.assign(H + 1, 0);
+
+    struct Open {
+        int lanes = 0;
+        std::vector<int> lane_piece;  // piece (global index) per used lane
+    } cur;
+    std::vector<int64_t> wslot_src;   // slots of the open workgroup, [F][L]
+    std::vector<int32_t> wslot_d;
+
+    auto open_wg = [&]() {
+        cur.lanes = 0;
+        cur.lane_piece.clear();
+        wslot_src.assign((size_t)F * L, -1);
+        wslot_d.assign((size_t)F * L, 0);
+    };
+    auto close_wg = [&](int h) {
+        if (cur.lanes == 0) return;
+        WgDesc w{};
+        w.band = h;
+        w.slot_base = p.n_slots;
+        w.meta_base = (int32_t)p.lane_meta.size();
+        const int first_piece = cur.lane_piece.front();
+        const int last_piece = cur.lane_piece.back();
+        w.piece_base = first_piece;
+        w.npiece = last_piece - first_piece + 1;
+        int maxd = 0;
+        for (int i = 0; i < F * L; ++i)
+            if (wslot_src[i] >= 0) maxd = std::max(maxd, wslot_d[i]);
+        w.maxd = maxd;
+        // lane -> local piece (padding lanes join the last piece); runs end at a
+        // piece change or at the end of each 16-lane group
+        std::vector<int> lp(L);
+        for (int i = 0; i < L; ++i)
+            lp[i] = (i < cur.lanes ? cur.lane_piece[i] : last_piece) - first_piece;
+        int run = 0;
+        std::vector<int> run0(w.npiece, -1), run1(w.npiece, -1);
+        for (int i = 0; i < L; ++i) {
+            const bool end = (i % kRunLanes == kRunLanes - 1) || (i == L - 1) || lp[i + 1] != lp[i];
+            int slot = kSlotNone;
+            if (end) {
+                slot = run++;
+                if (run0[lp[i]] < 0) run0[lp[i]] = slot;
+                run1[lp[i]] = slot + 1;
+            }
+            p.lane_meta.push_back((lp[i] << 16) | slot);
+        }
+        w.nrun = run;
+        for (int q = 0; q < w.npiece; ++q) {
+            p.piece[first_piece + q].run0 = run0[q];
+            p.piece[first_piece + q].run1 = run1[q];
+        }
+        p.nrun_max = std::max(p.nrun_max, run);
+        p.npiece_max = std::max(p.npiece_max, w.npiece);
+        for (int i = 0; i < F * L; ++i) {
+            p.slot_src.push_back(wslot_src[i]);
+            p.slot_off.push_back(wslot_src[i] >= 0 ? maxd - wslot_d[i] : maxd);
+        }
+        p.n_slots += (int64_t)F * L;
+        p.wg.push_back(w);
+        open_wg();
+    };
+
+    open_wg();
+    for (int h = 0; h < H; ++h) {
+        p.band_wg0[h] = (int)p.wg.size();
+        const int64_t zstride = p.mb_inner >> h;
+        for (int t = 0; t < T; ++t) {
+            const int M = d->n_filters[t * H + h];
+            if (M == 0) continue;
+            const int nl = (M + F - 1) / F;
+            SegDesc& sg = p.seg[(size_t)t * H + h];
+            sg.zoff = p.zw_elems;
+            sg.npiece = 0;
+            int placed = 0;
+            while (placed < nl) {
+                const int cur_pieces =
+                    cur.lanes ? cur.lane_piece.back() - cur.lane_piece.front() + 1 : 0;
+                if (cur.lanes == L || cur_pieces >= kMaxPiecesPerGroup) close_wg(h);
+                const int take = std::min(nl - placed, L - cur.lanes);
+                PieceDesc pc{};
+                pc.zoff = p.zw_elems;
+                pc.tmpl = t;
+                p.zw_elems += zstride;
+                const int pid = (int)p.piece.size();
+                p.piece.push_back(pc);
+                sg.npiece++;
+                for (int i = 0; i < take; ++i) {
+                    const int lane = cur.lanes + i;
+                    for (int f = 0; f < F; ++f) {
+                        const int j = (placed + i) * F + f;
+                        if (j >= M) break;
+                        const int64_t src = moff[t * H + h] + j;
+                        wslot_src[(size_t)f * L + lane] = src;
+                        wslot_d[(size_t)f * L + lane] = d->delay[src];
+                    }
+                    cur.lane_piece.push_back(pid);
+                }
+                cur.lanes += take;
+                placed += take;
+            }
+        }
+        close_wg(h);
+    }
+    p.band_wg0[H] = (int)p.wg.size();
+
+    p.lds_filter = p.xcap * 4 + L * (kTile + 1) * 8 + kTile * p.nrun_max * 8 + p.npiece_max * 8 +
+                   L * 4 + p.npiece_max * 8;
+    p.lds_stage = ((p.td - 1) + p.mb_inner + (p.td - 1) + p.mb_inner / 2 + p.td) * 4;
+    p.lds_up = 2 * (p.hu_len + p.mb_inner / 2) * 8 + p.tu * 4;
+    if (p.lds_filter > kMaxLds || p.lds_stage > kMaxLds || p.lds_up > kMaxLds) return SPIIR_EINVAL;
+
+    size_t fp = 0;
+    fp += (size_t)p.n_slots * (5 * sizeof(c32) + sizeof(int32_t));
+    fp += p.wg.size() * sizeof(WgDesc) + p.piece.size() * sizeof(PieceDesc);
+    fp += p.seg.size() * sizeof(SegDesc) + p.lane_meta.size() * sizeof(int32_t);
+    fp += (size_t)p.ring_total * sizeof(float) + (size_t)(p.td + p.tu) * sizeof(float);
+    fp += (size_t)p.zw_elems * sizeof(c32);
+    fp += (size_t)T * H * p.hu_len * sizeof(c32) + (size_t)T * sizeof(int32_t) + sizeof(BankDev);
+    p.footprint = fp;
+    return SPIIR_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+spiir_profile_data g_prof_acc{};
+
+hipEvent_t prof_event()
+{
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Returns every event of the recorded launches to the pool once (consecutive
+// launches share their boundary events).
+void recycle_prof_events()
+{
+    std::vector<hipEvent_t> seen;
+    for (auto& r : g_prof_recs) {
+        if (std::find(seen.begin(), seen.end(), r.a) == seen.end()) seen.push_back(r.a);
+        if (std::find(seen.begin(), seen.end(), r.b) == seen.end()) seen.push_back(r.b);
+    }
+    for (auto ev : seen) g_prof_pool.push_back(ev);
+    g_prof_recs.clear();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- the bank
+
+struct spiir_bank {
+    Plan plan;
+    int device = 0;
+    int64_t done = 0;
+    bool poisoned = false;
+    hipEvent_t ev = nullptr;
+    bool ev_recorded = false;
+    // device memory
+    c32 *a = nullptr, *b = nullptr, *dc = nullptr, *y = nullptr, *ys = nullptr;
+    int32_t* off = nullptr;
+    WgDesc* wg = nullptr;
+    PieceDesc* piece = nullptr;
+    SegDesc* seg = nullptr;
+    int32_t* lane_meta = nullptr;
+    float* rings = nullptr;
+    float* hd = nullptr;
+    float* hu = nullptr;
+    c32* zw = nullptr;
+    c32* uphist = nullptr;
+    int32_t* flags = nullptr;
+    BankDev* bd = nullptr;
+};
+
+namespace {
+
+template <class T>
+hipError_t dalloc(T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+
+void free_bank(spiir_bank* b)
+{
+    if (!b) return;
+    void* ptrs[] = {b->a,     b->b,     b->dc, b->y,  b->ys, b->off, b->wg,     b->piece, b->seg,
+                    b->lane_meta, b->rings, b->hd, b->hu, b->zw, b->uphist, b->flags, b->bd};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    delete b;
+}
+
+int zero_state(spiir_bank* b, hipStream_t s)
+{
+    const Plan& p = b->plan;
+    int e = 0;
+    e |= launch_fill(b->y, p.n_slots * (int64_t)sizeof(c32), s);
+    e |= launch_fill(b->ys, p.n_slots * (int64_t)sizeof(c32), s);
+    e |= launch_fill(b->rings, p.ring_total * (int64_t)sizeof(float), s);
+    e |= launch_fill(b->uphist, (int64_t)p.T * p.H * p.hu_len * (int64_t)sizeof(c32), s);
+    e |= launch_fill(b->flags, (int64_t)p.T * (int64_t)sizeof(int32_t), s);
+    return e;
+}
+
+int64_t state_bytes(const Plan& p)
+{
+    return 64 + p.n_slots * 2 * (int64_t)sizeof(c32) + p.ring_total * (int64_t)sizeof(float) +
+           (int64_t)p.T * p.H * p.hu_len * (int64_t)sizeof(c32) + (int64_t)p.T * 4;
+}
+
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t T, H, F, L, C, precision;
+    int64_t n_slots, ring_total, done;
+    int64_t hist;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* spiir_strerror(int status)
+{
+    switch (status) {
+    case SPIIR_OK: return "ok";
+    case SPIIR_EINVAL: return "invalid argument";
+    case SPIIR_ENOMEM: return "out of device memory";
+    case SPIIR_EDEVICE: return "device error (bank poisoned)";
+    case SPIIR_EORDER: return "request order violated";
+    case SPIIR_ENONFINITE: return "non-finite state or output";
+    default: return "unknown status";
+    }
+}
+
+int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info)
+{
+    if (!info) return SPIIR_EINVAL;
+    Plan p;
+    int rc;
+    try {
+        rc = make_plan(desc, p);
+    } catch (const std::bad_alloc&) {
+        return SPIIR_ENOMEM;
+    }
+    if (rc) return rc;
+    info->total_filters = p.total_filters;
+    info->filter_slots = p.n_slots;
+    info->n_groups = (int32_t)p.wg.size();
+    info->n_pieces = (int32_t)p.piece.size();
+    info->lanes_per_group = p.L;
+    info->filters_per_lane = p.F;
+    info->lds_bytes = p.lds_filter;
+    info->carry_chunk = p.C;
+    info->footprint = p.footprint;
+    return SPIIR_OK;
+}
+
+int spiir_footprint(const spiir_bank_desc* desc, size_t* bytes)
+{
+    if (!bytes) return SPIIR_EINVAL;
+    spiir_plan_info info;
+    int rc = spiir_plan(desc, &info);
+    if (rc) return rc;
+    *bytes = info.footprint;
+    return SPIIR_OK;
+}
+
+int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
+{
+    if (!out) return SPIIR_EINVAL;
+    *out = nullptr;
+    spiir_bank* b = nullptr;
+    try {
+        b = new spiir_bank();
+        int rc = make_plan(desc, b->plan);
+        if (rc) {
+            delete b;
+            return rc;
+        }
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return SPIIR_ENOMEM;
+    }
+    Plan& p = b->plan;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device >= ndev) {
+        delete b;
+        return ndev == 0 ? SPIIR_EDEVICE : SPIIR_EINVAL;
+    }
+    b->device = desc->device;
+    if (hipSetDevice(b->device) != hipSuccess) {
+        delete b;
+        return SPIIR_EDEVICE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+
+    bool ok = true;
+    ok &= dalloc(&b->a, p.n_slots) == hipSuccess;
+    ok &= dalloc(&b->b, p.n_slots) == hipSuccess;
+    ok &= dalloc(&b->dc, p.n_slots) == hipSuccess;
+    ok &= dalloc(&b->y, p.n_slots) == hipSuccess;
+    ok &= dalloc(&b->ys, p.n_slots) == hipSuccess;
+    ok &= dalloc(&b->off, p.n_slots) == hipSuccess;
+    ok &= dalloc(&b->wg, p.wg.size()) == hipSuccess;
+    ok &= dalloc(&b->piece, p.piece.size()) == hipSuccess;
+    ok &= dalloc(&b->seg, p.seg.size()) == hipSuccess;
+    ok &= dalloc(&b->lane_meta, p.lane_meta.size()) == hipSuccess;
+    ok &= dalloc(&b->rings, p.ring_total) == hipSuccess;
+    ok &= dalloc(&b->hd, p.td) == hipSuccess;
+    ok &= dalloc(&b->hu, p.tu) == hipSuccess;
+    ok &= dalloc(&b->zw, p.zw_elems) == hipSuccess;
+    ok &= dalloc(&b->uphist, (size_t)p.T * p.H * p.hu_len) == hipSuccess;
+    ok &= dalloc(&b->flags, p.T) == hipSuccess;
+    ok &= dalloc(&b->bd, 1) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_bank(b);
+        return SPIIR_ENOMEM;
+    }
+
+    // tables in lane order; coefficients go through the FP64 prep kernel
+    c64* da = nullptr;
+    c64* db = nullptr;
+    std::vector<c64> ha((size_t)p.n_slots), hb((size_t)p.n_slots);
+    for (int64_t g = 0; g < p.n_slots; ++g) {
+        const int64_t src = p.slot_src[g];
+        if (src >= 0) {
+            ha[g] = c64{desc->a1[2 * src], desc->a1[2 * src + 1]};
+            hb[g] = c64{desc->b0[2 * src], desc->b0[2 * src + 1]};
+        } else {
+            ha[g] = c64{0.0, 0.0};
+            hb[g] = c64{0.0, 0.0};
+        }
+    }
+    std::vector<float> hd(p.td, 1.0f), hu(p.tu, 1.0f);
+    if (p.H > 1) {
+        for (int i = 0; i < p.td; ++i) hd[i] = (float)desc->h_down[i];
+        for (int i = 0; i < p.tu; ++i) hu[i] = (float)desc->h_up[i];
+    }
+    BankDev bd{};
+    bd.T = p.T;
+    bd.H = p.H;
+    bd.L = p.L;
+    bd.F = p.F;
+    bd.C = p.C;
+    bd.precision = p.precision;
+    bd.td = p.td;
+    bd.tu = p.tu;
+    bd.hu_len = p.hu_len;
+    bd.max_block = p.mb_inner;
+    bd.xcap = p.xcap;
+    bd.nrun_max = p.nrun_max;
+    bd.npiece_max = p.npiece_max;
+    for (int h = 0; h < p.H; ++h) {
+        bd.S[h] = p.S[h];
+        bd.ring_mask[h] = p.ring_mask[h];
+        bd.ring_off[h] = p.ring_off[h];
+    }
+    for (int h = 0; h <= p.H; ++h) bd.band_wg0[h] = p.band_wg0[h];
+    bd.wg = b->wg;
+    bd.piece = b->piece;
+    bd.seg = b->seg;
+    bd.lane_meta = b->lane_meta;
+    bd.a = b->a;
+    bd.b = b->b;
+    bd.dc = b->dc;
+    bd.off = b->off;
+    bd.y = b->y;
+    bd.ys = b->ys;
+    bd.rings = b->rings;
+    bd.hd = b->hd;
+    bd.hu = b->hu;
+    bd.zw = b->zw;
+    bd.uphist = b->uphist;
+    bd.flags = b->flags;
+
+    hipError_t e = hipSuccess;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    if (hipMalloc((void**)&da, sizeof(c64) * std::max<int64_t>(p.n_slots, 1)) != hipSuccess ||
+        hipMalloc((void**)&db, sizeof(c64) * std::max<int64_t>(p.n_slots, 1)) != hipSuccess) {
+        if (da) (void)hipFree(da);
+        if (db) (void)hipFree(db);
+        (void)hipGetLastError();
+        free_bank(b);
+        return SPIIR_ENOMEM;
+    }
+    up(da, ha.data(), sizeof(c64) * p.n_slots);
+    up(db, hb.data(), sizeof(c64) * p.n_slots);
+    up(b->off, p.slot_off.data(), sizeof(int32_t) * p.n_slots);
+    up(b->wg, p.wg.data(), sizeof(WgDesc) * p.wg.size());
+    up(b->piece, p.piece.data(), sizeof(PieceDesc) * p.piece.size());
+    up(b->seg, p.seg.data(), sizeof(SegDesc) * p.seg.size());
+    up(b->lane_meta, p.lane_meta.data(), sizeof(int32_t) * p.lane_meta.size());
+    up(b->hd, hd.data(), sizeof(float) * p.td);
+    up(b->hu, hu.data(), sizeof(float) * p.tu);
+    up(b->bd, &bd, sizeof(BankDev));
+    if (e == hipSuccess) e = (hipError_t)launch_prep(da, db, p.n_slots, p.C, b->a, b->b, b->dc, s);
+    if (e == hipSuccess) e = (hipError_t)zero_state(b, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(da);
+    (void)hipFree(db);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_bank(b);
+        return SPIIR_EDEVICE;
+    }
+    *out = b;
+    return SPIIR_OK;
+}
+
+int spiir_process_batch(int32_t n_req, const spiir_request* req, void* stream)
+{
+    if (n_req < 1 || n_req > SPIIR_MAX_BATCH || !req) return SPIIR_EINVAL;
+    for (int r = 0; r < n_req; ++r) {
+        const spiir_request& q = req[r];
+        if (!q.bank) return SPIIR_EINVAL;
+        if (q.bank->poisoned) return SPIIR_EDEVICE;
+        const Plan& p = q.bank->plan;
+        if (q.n <= 0 || q.n > p.max_block || q.n % (1 << (p.H - 1)) != 0) return SPIIR_EINVAL;
+        if (!q.x_dev || !q.z_dev || q.ldz < q.n) return SPIIR_EINVAL;
+        const Plan& p0 = req[0].bank->plan;
+        if (q.bank->device != req[0].bank->device || p.F != p0.F || p.L != p0.L ||
+            p.precision != p0.precision)
+            return SPIIR_EINVAL;
+        for (int s = 0; s < r; ++s)
+            if (req[s].bank == q.bank) return SPIIR_EORDER;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(req[0].bank->device) != hipSuccess) return SPIIR_EDEVICE;
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < n_req; ++r)
+        if (req[r].bank->ev_recorded && e == hipSuccess) e = hipStreamWaitEvent(s, req[r].bank->ev, 0);
+
+    std::unique_lock<std::mutex> lk(g_prof_mu);
+    const bool prof = g_prof_on;
+    if (!prof) lk.unlock();
+
+    int64_t maxn = 0;
+    for (int r = 0; r < n_req; ++r) maxn = std::max<int64_t>(maxn, req[r].n);
+    int F = req[0].bank->plan.F, L = req[0].bank->plan.L, prec = req[0].bank->plan.precision;
+    for (int64_t c0 = 0; c0 < maxn && e == hipSuccess; c0 += kInner) {
+        LaunchArgs A;
+        std::memset(&A, 0, sizeof(A));
+        int rmap[SPIIR_MAX_BATCH];
+        int lds_f = 0, lds_s = 0, lds_u = 0, nwg = 0, ntm = 0, maxH = 0;
+        for (int r = 0; r < n_req; ++r) {
+            const spiir_request& q = req[r];
+            if (q.n <= c0) continue;
+            spiir_bank* b = q.bank;
+            const Plan& p = b->plan;
+            const int k = A.nreq++;
+            rmap[k] = r;
+            ReqArg& ra = A.req[k];
+            ra.bd = b->bd;
+            ra.x = q.x_dev + c0;
+            ra.z = reinterpret_cast<c32*>(q.z_dev) + c0;
+            ra.ldz = q.ldz;
+            ra.s0 = b->done;
+            ra.n = (int32_t)std::min<int64_t>(kInner, q.n - c0);
+            ra.H = p.H;
+            lds_f = std::max(lds_f, p.lds_filter);
+            lds_s = std::max(lds_s, p.lds_stage);
+            lds_u = std::max(lds_u, p.lds_up);
+            maxH = std::max(maxH, p.H);
+        }
+        // filter workgroups: band-major across requests (longest bands first)
+        A.cum[0] = 0;
+        for (int h = 0; h < maxH; ++h)
+            for (int k = 0; k < A.nreq; ++k) {
+                const Plan& p = req[rmap[k]].bank->plan;
+                if (h >= p.H) continue;
+                const int cnt = p.band_wg0[h + 1] - p.band_wg0[h];
+                if (cnt == 0) continue;
+                A.seg_req[A.nseg] = (int16_t)k;
+                A.seg_band[A.nseg] = (int16_t)h;
+                A.cum[A.nseg + 1] = A.cum[A.nseg] + cnt;
+                A.nseg++;
+                nwg += cnt;
+            }
+        A.tcum[0] = 0;
+        for (int k = 0; k < A.nreq; ++k) {
+            A.tcum[k + 1] = A.tcum[k] + req[rmap[k]].bank->plan.T;
+            ntm += req[rmap[k]].bank->plan.T;
+        }
+
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        if (prof)
+            for (int i = 0; i < 4; ++i) {
+                ev[i] = prof_event();
+                if (ev[i]) (void)hipEventRecord(ev[i], s);
+                if (i == 0) e = (hipError_t)launch_stage(A, lds_s, s);
+                else if (i == 1 && e == hipSuccess && nwg > 0)
+                    e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
+                else if (i == 2 && e == hipSuccess)
+                    e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
+            }
+        else {
+            e = (hipError_t)launch_stage(A, lds_s, s);
+            if (e == hipSuccess && nwg > 0) e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
+            if (e == hipSuccess) e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
+        }
+        if (prof) {
+            for (int i = 0; i < 3; ++i)
+                if (ev[i] && ev[i + 1]) g_prof_recs.push_back(ProfRec{i, ev[i], ev[i + 1]});
+        }
+        for (int k = 0; k < A.nreq; ++k) req[rmap[k]].bank->done += A.req[k].n;
+    }
+    if (lk.owns_lock()) lk.unlock();
+    for (int r = 0; r < n_req && e == hipSuccess; ++r) {
+        e = hipEventRecord(req[r].bank->ev, s);
+        req[r].bank->ev_recorded = true;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        for (int r = 0; r < n_req; ++r) req[r].bank->poisoned = true;
+        return SPIIR_EDEVICE;
+    }
+    return SPIIR_OK;
+}
+
+int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
+                        int64_t ldz, void* stream)
+{
+    spiir_request r{bank, x_dev, n, z_dev, ldz};
+    return spiir_process_batch(1, &r, stream);
+}
+
+static int bank_sync(spiir_bank* b)
+{
+    if (hipSetDevice(b->device) != hipSuccess) return SPIIR_EDEVICE;
+    if (b->ev_recorded && hipEventSynchronize(b->ev) != hipSuccess) {
+        b->poisoned = true;
+        return SPIIR_EDEVICE;
+    }
+    return SPIIR_OK;
+}
+
+int spiir_reset(spiir_bank* b)
+{
+    if (!b) return SPIIR_EINVAL;
+    if (b->poisoned) return SPIIR_EDEVICE;
+    int rc = bank_sync(b);
+    if (rc) return rc;
+    hipError_t e = (hipError_t)zero_state(b, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        b->poisoned = true;
+        return SPIIR_EDEVICE;
+    }
+    b->done = 0;
+    return SPIIR_OK;
+}
+
+int spiir_state_size(const spiir_bank* b, size_t* bytes)
+{
+    if (!b || !bytes) return SPIIR_EINVAL;
+    *bytes = (size_t)state_bytes(b->plan);
+    return SPIIR_OK;
+}
+
+int spiir_save_state(spiir_bank* b, void* host_buf, void* stream)
+{
+    if (!b || !host_buf) return SPIIR_EINVAL;
+    if (b->poisoned) return SPIIR_EDEVICE;
+    const Plan& p = b->plan;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(b->device) != hipSuccess) return SPIIR_EDEVICE;
+    hipError_t e = hipSuccess;
+    if (b->ev_recorded) e = hipStreamWaitEvent(s, b->ev, 0);
+    StateHeader hdr{kStateMagic, kStateVersion, p.T, p.H, p.F, p.L, p.C, p.precision,
+                    p.n_slots, p.ring_total, b->done, (int64_t)p.T * p.H * p.hu_len};
+    char* o = (char*)host_buf;
+    std::memset(o, 0, 64);
+    std::memcpy(o, &hdr, sizeof(hdr));
+    o += 64;
+    auto dn = [&](const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(o, src, bytes, hipMemcpyDeviceToHost, s);
+        o += bytes;
+    };
+    dn(b->y, sizeof(c32) * p.n_slots);
+    dn(b->ys, sizeof(c32) * p.n_slots);
+    dn(b->rings, sizeof(float) * p.ring_total);
+    dn(b->uphist, sizeof(c32) * (size_t)p.T * p.H * p.hu_len);
+    dn(b->flags, sizeof(int32_t) * p.T);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        b->poisoned = true;
+        return SPIIR_EDEVICE;
+    }
+    return SPIIR_OK;
+}
+
+int spiir_load_state(spiir_bank* b, const void* host_buf, void* stream)
+{
+    if (!b || !host_buf) return SPIIR_EINVAL;
+    if (b->poisoned) return SPIIR_EDEVICE;
+    const Plan& p = b->plan;
+    StateHeader hdr;
+    std::memcpy(&hdr, host_buf, sizeof(hdr));
+    if (hdr.magic != kStateMagic || hdr.version != kStateVersion || hdr.T != p.T || hdr.H != p.H ||
+        hdr.F != p.F || hdr.L != p.L || hdr.C != p.C || hdr.n_slots != p.n_slots ||
+        hdr.ring_total != p.ring_total || hdr.hist != (int64_t)p.T * p.H * p.hu_len || hdr.done < 0)
+        return SPIIR_EINVAL;
+    int rc = bank_sync(b);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const char* o = (const char*)host_buf + 64;
+    hipError_t e = hipSuccess;
+    auto upl = [&](void* dst, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, o, bytes, hipMemcpyHostToDevice, s);
+        o += bytes;
+    };
+    upl(b->y, sizeof(c32) * p.n_slots);
+    upl(b->ys, sizeof(c32) * p.n_slots);
+    upl(b->rings, sizeof(float) * p.ring_total);
+    upl(b->uphist, sizeof(c32) * (size_t)p.T * p.H * p.hu_len);
+    upl(b->flags, sizeof(int32_t) * p.T);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        b->poisoned = true;
+        return SPIIR_EDEVICE;
+    }
+    b->done = hdr.done;
+    return SPIIR_OK;
+}
+
+int spiir_status(spiir_bank* b, int32_t* template_flags)
+{
+    if (!b) return SPIIR_EINVAL;
+    if (b->poisoned) return SPIIR_EDEVICE;
+    int rc = bank_sync(b);
+    if (rc) return rc;
+    std::vector<int32_t> f(b->plan.T);
+    if (hipMemcpy(f.data(), b->flags, sizeof(int32_t) * f.size(), hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+        b->poisoned = true;
+        return SPIIR_EDEVICE;
+    }
+    bool any = false;
+    for (size_t t = 0; t < f.size(); ++t) {
+        any |= f[t] != 0;
+        if (template_flags) template_flags[t] = f[t] != 0;
+    }
+    return any ? SPIIR_ENONFINITE : SPIIR_OK;
+}
+
+int spiir_destroy(spiir_bank* b)
+{
+    if (!b) return SPIIR_OK;
+    (void)hipSetDevice(b->device);
+    if (b->ev_recorded) (void)hipEventSynchronize(b->ev);
+    free_bank(b);
+    return SPIIR_OK;
+}
+
+int spiir_samples_done(const spiir_bank* b, int64_t* samples)
+{
+    if (!b || !samples) return SPIIR_EINVAL;
+    *samples = b->done;
+    return SPIIR_OK;
+}
+
+int spiir_profile_enable(int enable)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recycle_prof_events();
+    std::memset(&g_prof_acc, 0, sizeof(g_prof_acc));
+    g_prof_on = enable != 0;
+    return SPIIR_OK;
+}
+
+int spiir_profile_read(spiir_profile_data* out)
+{
+    if (!out) return SPIIR_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    int rc = SPIIR_OK;
+    for (auto& r : g_prof_recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            rc = SPIIR_EDEVICE;
+            continue;
+        }
+        g_prof_acc.launches[r.kind] += 1;
+        g_prof_acc.ms[r.kind] += ms;
+    }
+    recycle_prof_events();
+    *out = g_prof_acc;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal layout shared by the host library and the gfx950 kernels.
+//
+// Work decomposition of the filter bank (§2.1, Eqs. 7-8):
+//   * a workgroup owns L = 64*W lanes; each lane runs F filters of ONE
+//     (template, band) segment, with the filter state in VGPRs;
+//   * the segments of one band are laid end to end in lane space
+//     (ceil(M/F) lanes each) and cut into workgroups of L lanes, so a segment
+//     that straddles a workgroup boundary becomes two "pieces", each of which
+//     writes its own partial band output to the workspace;
+//   * per sample, each lane adds its F filters (pairwise), stores the partial
+//     to LDS, and every kTile samples the workgroup reduces the partials of
+//     each piece in two fixed-order levels (16-lane runs, then runs), so the
+//     result does not depend on anything outside the bank.
+#pragma once
+#include <cstdint>
+
+#include "spiir.h"
+
+namespace spiir {
+
+constexpr int kTile = 16;        // samples per reduction tile (R)
+constexpr int kRunLanes = 16;    // lanes per level-1 run group
+constexpr int kMaxReq = SPIIR_MAX_BATCH;
+constexpr int kMaxBands = SPIIR_MAX_BANDS;
+constexpr int kMaxPiecesPerGroup = 128;
+constexpr int kSlotNone = 0xffff;
+
+// Largest workgroup of the filter kernel for F filters per lane: with 8
+// filters a lane needs more than 128 VGPRs, so at most 2 waves per SIMD.
+constexpr int filter_max_threads(int F) { return F >= 8 ? 512 : 1024; }
+
+struct c32 {
+    float x, y;
+};
+struct c64 {
+    double x, y;
+};
+
+// One workgroup of the filter kernel.
+struct WgDesc {
+    int32_t band;
+    int32_t maxd;        // largest delay among its filters: LDS window reach
+    int32_t npiece;
+    int32_t nrun;
+    int64_t slot_base;   // filter slot (f, lane) lives at slot_base + f*L + lane
+    int32_t meta_base;   // L lane-meta words: (piece << 16) | run slot (or kSlotNone)
+    int32_t piece_base;  // first PieceDesc
+};
+
+// A contiguous lane range of one (template, band) segment inside a workgroup.
+struct PieceDesc {
+    int64_t zoff;  // workspace offset (complex elements) of its partial band output
+    int32_t run0;  // its level-2 runs are [run0, run1) (workgroup-local)
+    int32_t run1;
+    int32_t tmpl;
+    int32_t pad;
+};
+
+// Per (template, band): its pieces' outputs, consecutive with stride max_block >> h.
+struct SegDesc {
+    int64_t zoff;
+    int32_t npiece;
+    int32_t pad;
+};
+
+// Device-resident constant description of a bank (one copy per bank).
+struct BankDev {
+    int32_t T, H, L, F, C, precision;
+    int32_t td, tu, hu_len, max_block;
+    int32_t xcap;                   // LDS window capacity, floats
+    int32_t nrun_max;               // level-2 run slots per tile row
+    int32_t npiece_max;
+    int32_t pad0;
+    int32_t S[kMaxBands];           // window sub-block length per band
+    int32_t ring_mask[kMaxBands];   // ring size - 1 per band (power of two)
+    int64_t ring_off[kMaxBands];    // band ring offset in `rings`
+    int32_t band_wg0[kMaxBands + 1];
+    const WgDesc* wg;
+    const PieceDesc* piece;
+    const SegDesc* seg;             // [T*H]
+    const int32_t* lane_meta;
+    const c32* a;                   // per slot: fl32(a1)
+    const c32* b;                   // per slot: fl32(b0)
+    const c32* dc;                  // per slot: a1^C - fl32(a1)^C (FP64 -> FP32)
+    const int32_t* off;             // per slot: LDS offset = group maxd - d
+    c32* y;                         // per slot: state y[k-1]
+    c32* ys;                        // per slot: state at the current chunk start
+    float* rings;                   // per-band input history rings
+    const float* hd;
+    const float* hu;
+    c32* zw;                        // per-piece band outputs of the current block
+    c32* uphist;                    // [T][H][hu_len] last acc samples per band
+    int32_t* flags;                 // [T] sticky non-finite flags
+};
+
+struct ReqArg {
+    const BankDev* bd;
+    const float* x;
+    c32* z;
+    int64_t ldz;
+    int64_t s0;   // absolute base-rate index of the block's first sample
+    int32_t n;
+    int32_t H;
+};
+
+// Everything one launch sequence needs, passed by value as kernel arguments.
+struct LaunchArgs {
+    int32_t nreq;
+    int32_t nseg;                                  // (band, request) WG ranges
+    ReqArg req[kMaxReq];
+    int32_t cum[kMaxReq * kMaxBands + 1];          // prefix of WG counts
+    int16_t seg_req[kMaxReq * kMaxBands];
+    int16_t seg_band[kMaxReq * kMaxBands];
+    int32_t tcum[kMaxReq + 1];                     // prefix of templates
+};
+
+// Launchers (spiir_kernels.hip).  All return hipError_t as int.
+int launch_stage(const LaunchArgs& a, int lds_bytes, void* stream);
+int launch_filter(int F, int precision, const LaunchArgs& a, int nblocks, int L, int lds_bytes,
+                  void* stream);
+int launch_upadd(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream);
+int launch_prep(const c64* a, const c64* b, int64_t n, int C, c32* fa, c32* fb, c32* fdc,
+                void* stream);
+int launch_fill(void* p, int64_t bytes, void* stream);
+int filter_max_lds();
+
+}  // namespace spiir

@@ -1,0 +1,460 @@
+// gfx950 kernels of the SPIIR library.
+//
+//   k_stage   append a block to the band-0 input ring and run the /2 FIR
+//             cascade (§2.2, resampling of Eq. 9 as a causal FIR) once per
+//             stream, writing every band's new samples to its ring;
+//   k_filter  the filter bank: Eq. 7 per filter with the state in VGPRs,
+//             Eq. 8 as a deterministic two-level LDS reduction per piece;
+//   k_upadd   per template: sum a band's pieces, add the x2 upsampled lower
+//             band (§2.2, Fig. "multi"), lowest band first, write z;
+//   k_prep    FP64 precompute of the carry corrections a1^C - fl32(a1)^C;
+//   k_fill    zero fill (used instead of memset so the sequence stays a plain
+//             chain of kernels).
+#include <hip/hip_runtime.h>
+
+#include "spiir_internal.h"
+
+namespace spiir {
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
+{
+    s = a + b;
+    const float bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+// ---------------------------------------------------------------------------
+// Input staging and the downsample cascade (one workgroup per request).
+// LDS: cur [td-1 + max_block] | nxt [td-1 + max_block/2] | taps [td]
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_stage(LaunchArgs args)
+{
+    extern __shared__ float sm[];
+    const ReqArg& q = args.req[blockIdx.x];
+    const BankDev* bd = q.bd;
+    const int n = q.n;
+    const int64_t s0 = q.s0;
+    const int H = bd->H;
+    float* ring0 = bd->rings + bd->ring_off[0];
+    const int64_t m0 = bd->ring_mask[0];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ring0[(s0 + i) & m0] = q.x[i];
+    if (H == 1) return;
+
+    const int td = bd->td;
+    const int hl = td - 1;
+    float* cur = sm;
+    float* nxt = sm + hl + bd->max_block;
+    float* hd = nxt + hl + bd->max_block / 2;
+    for (int i = threadIdx.x; i < td; i += blockDim.x) hd[i] = bd->hd[i];
+    for (int i = threadIdx.x; i < hl; i += blockDim.x) cur[i] = ring0[(s0 - hl + i) & m0];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) cur[hl + i] = q.x[i];
+    __syncthreads();
+
+    for (int h = 1; h < H; ++h) {
+        const int nh = n >> h;
+        const int64_t s0h = s0 >> h;
+        float* ring = bd->rings + bd->ring_off[h];
+        const int64_t mk = bd->ring_mask[h];
+        if (h < H - 1)
+            for (int i = threadIdx.x; i < hl; i += blockDim.x) nxt[i] = ring[(s0h - hl + i) & mk];
+        for (int m = threadIdx.x; m < nh; m += blockDim.x) {
+            // x_h[m] = sum_j h_d[j] x_{h-1}[2m - j]; cur[hl + i] holds x_{h-1} at block offset i
+            const float* src = cur + hl + 2 * m;
+            float s = 0.0f;
+            for (int j = 0; j < td; ++j) s = fmaf(hd[j], src[-j], s);
+            nxt[hl + m] = s;
+            ring[(s0h + m) & mk] = s;
+        }
+        __syncthreads();
+        float* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The filter bank.
+// LDS: xw [xcap] | pbuf [L][kTile+1] c32 | l2 [kTile][nrun_max] c32 |
+//      pzoff [npiece_max] i64 | lmeta [L] i32 | prun [npiece_max] int2
+// ---------------------------------------------------------------------------
+template <int F>
+__device__ __forceinline__ void lane_sum(float (&vr)[F], float (&vi)[F])
+{
+    // pairwise tree over the lane's filters; the result is left in element 0
+#pragma unroll
+    for (int s = 1; s < F; s *= 2)
+#pragma unroll
+        for (int i = 0; i + s < F; i += 2 * s) {
+            vr[i] += vr[i + s];
+            vi[i] += vi[i + s];
+        }
+}
+
+template <int F, bool COMP>
+__global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs args)
+{
+    extern __shared__ float sm[];
+    const int bid = blockIdx.x;
+    int lo = 0, hi = args.nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (args.cum[mid] <= bid) lo = mid;
+        else hi = mid;
+    }
+    const ReqArg& q = args.req[args.seg_req[lo]];
+    const int h = args.seg_band[lo];
+    const BankDev* bd = q.bd;
+    const WgDesc wg = bd->wg[bd->band_wg0[h] + (bid - args.cum[lo])];
+    const int L = blockDim.x;
+    const int tid = threadIdx.x;
+    const int nh = q.n >> h;
+    const int64_t s0h = q.s0 >> h;
+    const int64_t cmask = bd->C - 1;
+    const int nrun = bd->nrun_max;
+
+    float* xw = sm;
+    c32* pbuf = reinterpret_cast<c32*>(xw + bd->xcap);
+    c32* l2 = pbuf + L * (kTile + 1);
+    long long* pzoff = reinterpret_cast<long long*>(l2 + kTile * nrun);
+    int* lmeta = reinterpret_cast<int*>(pzoff + bd->npiece_max);
+    int2* prun = reinterpret_cast<int2*>(lmeta + L);
+
+    lmeta[tid] = bd->lane_meta[wg.meta_base + tid];
+    for (int p = tid; p < wg.npiece; p += L) {
+        const PieceDesc pd = bd->piece[wg.piece_base + p];
+        pzoff[p] = pd.zoff;
+        prun[p] = make_int2(pd.run0, pd.run1);
+    }
+
+    float ar[F], ai[F], br[F], bi[F], dr[F], di[F], yr[F], yi[F], sr[F], si[F];
+    int off[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const int64_t g = wg.slot_base + (int64_t)f * L + tid;
+        const c32 a = bd->a[g], b = bd->b[g], d = bd->dc[g], y = bd->y[g], ys = bd->ys[g];
+        ar[f] = a.x; ai[f] = a.y;
+        br[f] = b.x; bi[f] = b.y;
+        dr[f] = d.x; di[f] = d.y;
+        yr[f] = y.x; yi[f] = y.y;
+        sr[f] = ys.x; si[f] = ys.y;
+        off[f] = bd->off[g];
+    }
+    __syncthreads();
+
+    // level-1 role: sample row j1 of the 16-lane group q1; runs end where endmask is set
+    const int j1 = tid & (kTile - 1);
+    const int q1 = tid / kTile;
+    unsigned endmask = 0;
+    int slot0 = -1;
+#pragma unroll
+    for (int i = 0; i < kRunLanes; ++i) {
+        const int sl = lmeta[q1 * kRunLanes + i] & 0xffff;
+        if (sl != kSlotNone) {
+            endmask |= 1u << i;
+            if (slot0 < 0) slot0 = sl;
+        }
+    }
+
+    const int S = bd->S[h];
+    const float* ring = bd->rings + bd->ring_off[h];
+    const int64_t mk = bd->ring_mask[h];
+    c32* prow = pbuf + tid * (kTile + 1);
+
+    for (int kb = 0; kb < nh; kb += S) {
+        const int sub = min(S, nh - kb);
+        const int win = wg.maxd + sub;
+        __syncthreads();
+        const int64_t base = s0h + kb - wg.maxd;
+        for (int i = tid; i < win; i += L) xw[i] = ring[(base + i) & mk];
+        __syncthreads();
+
+        int k = kb;
+        while (k < kb + sub) {
+            const int64_t kabs = s0h + k;
+            int cnt = kTile - (int)(kabs & (kTile - 1));
+            if (cnt > kb + sub - k) cnt = kb + sub - k;
+            const float* xb[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) xb[f] = xw + off[f] + (k - kb);
+
+            if (cnt == kTile) {
+                // partials stay in registers until the tile ends, so no LDS store
+                // sits between the x loads of consecutive samples
+                float zr[kTile], zi[kTile];
+#pragma unroll
+                for (int j = 0; j < kTile; ++j) {
+                    float tr[F], ti[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        const float xv = xb[f][j];
+                        const float pr = br[f] * xv, pi = bi[f] * xv;
+                        const float nr = fmaf(ar[f], yr[f], fmaf(-ai[f], yi[f], pr));
+                        const float ni = fmaf(ar[f], yi[f], fmaf(ai[f], yr[f], pi));
+                        yr[f] = nr; yi[f] = ni;
+                        tr[f] = nr; ti[f] = ni;
+                    }
+                    lane_sum<F>(tr, ti);
+                    zr[j] = tr[0];
+                    zi[j] = ti[0];
+                }
+#pragma unroll
+                for (int j = 0; j < kTile; ++j) prow[j] = c32{zr[j], zi[j]};
+            } else {
+                for (int j = 0; j < cnt; ++j) {
+                    float tr[F], ti[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        const float xv = xb[f][j];
+                        const float pr = br[f] * xv, pi = bi[f] * xv;
+                        const float nr = fmaf(ar[f], yr[f], fmaf(-ai[f], yi[f], pr));
+                        const float ni = fmaf(ar[f], yi[f], fmaf(ai[f], yr[f], pi));
+                        yr[f] = nr; yi[f] = ni;
+                        tr[f] = nr; ti[f] = ni;
+                    }
+                    lane_sum<F>(tr, ti);
+                    prow[j] = c32{tr[0], ti[0]};
+                }
+            }
+
+            // carry correction after the last sample of an absolute chunk of C samples
+            if (((kabs + cnt) & cmask) == 0) {
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const float nr = fmaf(dr[f], sr[f], fmaf(-di[f], si[f], yr[f]));
+                    const float ni = fmaf(dr[f], si[f], fmaf(di[f], sr[f], yi[f]));
+                    yr[f] = nr; yi[f] = ni;
+                    sr[f] = nr; si[f] = ni;
+                }
+            }
+
+            __syncthreads();
+            // level 1: each thread sums one sample row over the runs of a 16-lane group
+            if (j1 < cnt) {
+                const c32* col = pbuf + (q1 * kRunLanes) * (kTile + 1) + j1;
+                c32* out = l2 + j1 * nrun;
+                int slot = slot0;
+                float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
+#pragma unroll
+                for (int i = 0; i < kRunLanes; ++i) {
+                    const c32 v = col[i * (kTile + 1)];
+                    if (COMP) {
+                        float e1, e2;
+                        two_sum(accr, v.x, accr, e1);
+                        two_sum(acci, v.y, acci, e2);
+                        er += e1;
+                        ei += e2;
+                    } else {
+                        accr += v.x;
+                        acci += v.y;
+                    }
+                    if (endmask & (1u << i)) {
+                        out[slot] = c32{accr + er, acci + ei};
+                        ++slot;
+                        accr = 0.0f; acci = 0.0f; er = 0.0f; ei = 0.0f;
+                    }
+                }
+            }
+            __syncthreads();
+            // level 2: each (piece, sample) sums its runs in order and writes the output
+            for (int task = tid; task < wg.npiece * kTile; task += L) {
+                const int p = task / kTile;
+                const int j = task & (kTile - 1);
+                if (j < cnt) {
+                    const int2 rr = prun[p];
+                    const c32* row = l2 + j * nrun;
+                    float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
+                    for (int s = rr.x; s < rr.y; ++s) {
+                        const c32 v = row[s];
+                        if (COMP) {
+                            float e1, e2;
+                            two_sum(accr, v.x, accr, e1);
+                            two_sum(acci, v.y, acci, e2);
+                            er += e1;
+                            ei += e2;
+                        } else {
+                            accr += v.x;
+                            acci += v.y;
+                        }
+                    }
+                    bd->zw[pzoff[p] + k + j] = c32{accr + er, acci + ei};
+                }
+            }
+            k += cnt;
+        }
+    }
+
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const int64_t g = wg.slot_base + (int64_t)f * L + tid;
+        bd->y[g] = c32{yr[f], yi[f]};
+        bd->ys[g] = c32{sr[f], si[f]};
+        bad |= !(isfinite(yr[f]) && isfinite(yi[f]));
+    }
+    if (bad) {
+        const int p = lmeta[tid] >> 16;
+        atomicOr(&bd->flags[bd->piece[wg.piece_base + p].tmpl], 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Upsample-and-add chain, one workgroup per (request, template).
+// LDS: e0 [hu_len + max_block/2] c32 | e1 [same] | taps [tu]
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_upadd(LaunchArgs args)
+{
+    extern __shared__ float sm[];
+    const int bid = blockIdx.x;
+    int r = 0;
+    while (r + 1 < args.nreq && args.tcum[r + 1] <= bid) ++r;
+    const ReqArg& q = args.req[r];
+    const BankDev* bd = q.bd;
+    const int t = bid - args.tcum[r];
+    const int H = bd->H, n = q.n, HU = bd->hu_len, tu = bd->tu, MB = bd->max_block;
+    const int ext = HU + MB / 2;
+    c32* cur = reinterpret_cast<c32*>(sm);
+    c32* nxt = cur + ext;
+    float* hu = reinterpret_cast<float*>(nxt + ext);
+    for (int i = threadIdx.x; i < tu; i += blockDim.x) hu[i] = bd->hu[i];
+    __syncthreads();
+
+    for (int h = H - 1; h >= 0; --h) {
+        const int nh = n >> h;
+        const SegDesc sg = bd->seg[(int64_t)t * H + h];
+        const int64_t stride = (int64_t)(MB >> h);
+        c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
+        if (h > 0)
+            for (int i = threadIdx.x; i < HU; i += blockDim.x) nxt[i] = hist[i];
+        for (int k = threadIdx.x; k < nh; k += blockDim.x) {
+            float vr = 0.0f, vi = 0.0f;
+            for (int p = 0; p < sg.npiece; ++p) {
+                const c32 u = bd->zw[sg.zoff + p * stride + k];
+                vr += u.x;
+                vi += u.y;
+            }
+            if (h < H - 1) {
+                // acc_h[k] += sum_i h_u[ph + 2i] * acc_{h+1}[(k >> 1) - i]
+                const int ph = k & 1;
+                const c32* src = cur + HU + (k >> 1);
+                for (int i = 0; ph + 2 * i < tu; ++i) {
+                    const float c = hu[ph + 2 * i];
+                    const c32 u = src[-i];
+                    vr = fmaf(c, u.x, vr);
+                    vi = fmaf(c, u.y, vi);
+                }
+            }
+            if (h == 0) q.z[(int64_t)t * q.ldz + k] = c32{vr, vi};
+            else nxt[HU + k] = c32{vr, vi};
+        }
+        __syncthreads();
+        if (h > 0) {
+            for (int i = threadIdx.x; i < HU; i += blockDim.x) hist[i] = nxt[nh + i];
+            c32* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 carry precompute and FP32 conversion of the tables (once, at create).
+// ---------------------------------------------------------------------------
+__global__ void k_prep(const c64* __restrict__ a, const c64* __restrict__ b, int64_t n, int C,
+                       c32* fa, c32* fb, c32* fdc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const c64 av = a[i], bv = b[i];
+    const float ar = (float)av.x, ai = (float)av.y;
+    const double tr = ar, ti = ai;  // fl32(a1) carried in FP64
+    double pr = 1.0, pi = 0.0, qr = 1.0, qi = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const double npr = pr * av.x - pi * av.y, npi = pr * av.y + pi * av.x;
+        const double nqr = qr * tr - qi * ti, nqi = qr * ti + qi * tr;
+        pr = npr; pi = npi;
+        qr = nqr; qi = nqi;
+    }
+    fa[i] = c32{ar, ai};
+    fb[i] = c32{(float)bv.x, (float)bv.y};
+    fdc[i] = c32{(float)(pr - qr), (float)(pi - qi)};
+}
+
+__global__ void k_fill(uint32_t* p, int64_t words)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+int launch_stage(const LaunchArgs& a, int lds_bytes, void* stream)
+{
+    hipLaunchKernelGGL(k_stage, dim3(a.nreq), dim3(256), lds_bytes, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+template <int F, bool COMP>
+static int launch_filter_t(const LaunchArgs& a, int nblocks, int L, int lds_bytes,
+                           hipStream_t s)
+{
+    if (lds_bytes > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_filter<F, COMP>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 lds_bytes);
+        if (e != hipSuccess) return (int)e;
+    }
+    hipLaunchKernelGGL((k_filter<F, COMP>), dim3(nblocks), dim3(L), lds_bytes, s, a);
+    return (int)hipGetLastError();
+}
+
+int launch_filter(int F, int precision, const LaunchArgs& a, int nblocks, int L, int lds_bytes,
+                  void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const bool comp = precision == SPIIR_FP32_COMPENSATED;
+    switch (F) {
+    case 1: return comp ? launch_filter_t<1, true>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<1, false>(a, nblocks, L, lds_bytes, s);
+    case 2: return comp ? launch_filter_t<2, true>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<2, false>(a, nblocks, L, lds_bytes, s);
+    case 4: return comp ? launch_filter_t<4, true>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<4, false>(a, nblocks, L, lds_bytes, s);
+    case 8: return comp ? launch_filter_t<8, true>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<8, false>(a, nblocks, L, lds_bytes, s);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_upadd(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream)
+{
+    hipLaunchKernelGGL(k_upadd, dim3(nblocks), dim3(256), lds_bytes, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+int launch_prep(const c64* a, const c64* b, int64_t n, int C, c32* fa, c32* fb, c32* fdc,
+                void* stream)
+{
+    if (n <= 0) return 0;
+    const int bs = 256;
+    const int64_t nb = (n + bs - 1) / bs;
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)nb), dim3(bs), 0, (hipStream_t)stream, a, b, n, C,
+                       fa, fb, fdc);
+    return (int)hipGetLastError();
+}
+
+int launch_fill(void* p, int64_t bytes, void* stream)
+{
+    if (bytes <= 0) return 0;
+    const int64_t words = bytes / 4;
+    int64_t nb = (words + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t*)p, words);
+    return (int)hipGetLastError();
+}
+
+int filter_max_lds() { return 160 * 1024; }
+
+}  // namespace spiir

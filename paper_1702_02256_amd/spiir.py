@@ -1,0 +1,305 @@
+"""Python binding of libspiir.so: argument marshalling only.
+
+Every step of the filtering path runs in the library's HIP kernels; this module
+converts numpy tables and torch device tensors into the C ABI's pointers and
+sizes.  The functions ``spiir_*`` mirror the C entry points one to one;
+``Bank`` is a thin object wrapper over them.  Importing this module fails
+loudly when the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspiir.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "spiir.h")
+
+SPIIR_OK = 0
+SPIIR_EINVAL = -1
+SPIIR_ENOMEM = -2
+SPIIR_EDEVICE = -3
+SPIIR_EORDER = -4
+SPIIR_ENONFINITE = -5
+SPIIR_FP32 = 0
+SPIIR_FP32_COMPENSATED = 1
+MAX_BATCH = 16
+
+_PRECISION = {"fp32": SPIIR_FP32, "fp32_compensated": SPIIR_FP32_COMPENSATED,
+              "compensated": SPIIR_FP32_COMPENSATED}
+
+
+class BankDesc(C.Structure):
+    _fields_ = [
+        ("n_templates", C.c_int32),
+        ("n_bands", C.c_int32),
+        ("base_rate_hz", C.c_int32),
+        ("n_filters", C.POINTER(C.c_int32)),
+        ("a1", C.POINTER(C.c_double)),
+        ("b0", C.POINTER(C.c_double)),
+        ("delay", C.POINTER(C.c_int32)),
+        ("n_taps_down", C.c_int32),
+        ("h_down", C.POINTER(C.c_double)),
+        ("n_taps_up", C.c_int32),
+        ("h_up", C.POINTER(C.c_double)),
+        ("max_block", C.c_int32),
+        ("precision", C.c_int32),
+        ("carry_chunk", C.c_int32),
+        ("filters_per_lane", C.c_int32),
+        ("waves_per_group", C.c_int32),
+        ("device", C.c_int32),
+    ]
+
+
+class Request(C.Structure):
+    _fields_ = [
+        ("bank", C.c_void_p),
+        ("x_dev", C.c_void_p),
+        ("n", C.c_int64),
+        ("z_dev", C.c_void_p),
+        ("ldz", C.c_int64),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("total_filters", C.c_int64),
+        ("filter_slots", C.c_int64),
+        ("n_groups", C.c_int32),
+        ("n_pieces", C.c_int32),
+        ("lanes_per_group", C.c_int32),
+        ("filters_per_lane", C.c_int32),
+        ("lds_bytes", C.c_int32),
+        ("carry_chunk", C.c_int32),
+        ("footprint", C.c_size_t),
+    ]
+
+
+class ProfileData(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 3), ("ms", C.c_double * 3)]
+
+
+class SpiirError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {spiir_strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def load_library():
+    """Load libspiir.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` (there is no fallback path)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "spiir_footprint": (C.c_int, [C.POINTER(BankDesc), C.POINTER(C.c_size_t)]),
+        "spiir_create": (C.c_int, [C.POINTER(BankDesc), vp, C.POINTER(vp)]),
+        "spiir_process_block": (C.c_int, [vp, vp, i64, vp, i64, vp]),
+        "spiir_process_batch": (C.c_int, [i32, C.POINTER(Request), vp]),
+        "spiir_reset": (C.c_int, [vp]),
+        "spiir_state_size": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "spiir_save_state": (C.c_int, [vp, vp, vp]),
+        "spiir_load_state": (C.c_int, [vp, vp, vp]),
+        "spiir_status": (C.c_int, [vp, C.POINTER(C.c_int32)]),
+        "spiir_destroy": (C.c_int, [vp]),
+        "spiir_strerror": (C.c_char_p, [C.c_int]),
+        "spiir_samples_done": (C.c_int, [vp, C.POINTER(C.c_int64)]),
+        "spiir_plan": (C.c_int, [C.POINTER(BankDesc), C.POINTER(PlanInfo)]),
+        "spiir_profile_enable": (C.c_int, [C.c_int]),
+        "spiir_profile_read": (C.c_int, [C.POINTER(ProfileData)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_symbols() -> list:
+    """Entry points declared in include/spiir.h."""
+    txt = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"\b(spiir_[a-z_]+)\s*\(", txt)))
+
+
+def spiir_strerror(code: int) -> str:
+    return load_library().spiir_strerror(int(code)).decode()
+
+
+def _check(rc: int, where: str) -> int:
+    if rc != SPIIR_OK:
+        raise SpiirError(rc, where)
+    return rc
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class _DescHolder:
+    """A BankDesc plus the numpy arrays its pointers refer to."""
+
+    def __init__(self, tables, max_block, precision="fp32", carry_chunk=0, filters_per_lane=0,
+                 waves_per_group=0, device=0):
+        self.nf = np.ascontiguousarray(tables.n_filters.reshape(-1), dtype=np.int32)
+        self.a1 = np.ascontiguousarray(np.asarray(tables.a1, np.complex128)).view(np.float64)
+        self.b0 = np.ascontiguousarray(np.asarray(tables.b0, np.complex128)).view(np.float64)
+        self.d = np.ascontiguousarray(tables.delay, dtype=np.int32)
+        self.hd = np.ascontiguousarray(tables.h_down, dtype=np.float64)
+        self.hu = np.ascontiguousarray(tables.h_up, dtype=np.float64)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        prec = _PRECISION[precision] if isinstance(precision, str) else int(precision)
+        self.desc = BankDesc(
+            n_templates=int(tables.n_filters.shape[0]),
+            n_bands=int(tables.n_filters.shape[1]),
+            base_rate_hz=int(tables.base_rate),
+            n_filters=ip(self.nf), a1=dp(self.a1), b0=dp(self.b0), delay=ip(self.d),
+            n_taps_down=len(self.hd), h_down=dp(self.hd),
+            n_taps_up=len(self.hu), h_up=dp(self.hu),
+            max_block=int(max_block), precision=prec, carry_chunk=int(carry_chunk),
+            filters_per_lane=int(filters_per_lane), waves_per_group=int(waves_per_group),
+            device=int(device))
+
+
+# ---------------------------------------------------------------- C-named functions
+
+
+def spiir_plan(tables, max_block, **kw) -> dict:
+    h = _DescHolder(tables, max_block, **kw)
+    info = PlanInfo()
+    _check(load_library().spiir_plan(C.byref(h.desc), C.byref(info)), "spiir_plan")
+    return {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+
+
+def spiir_footprint(tables, max_block, **kw) -> int:
+    h = _DescHolder(tables, max_block, **kw)
+    out = C.c_size_t()
+    _check(load_library().spiir_footprint(C.byref(h.desc), C.byref(out)), "spiir_footprint")
+    return int(out.value)
+
+
+def spiir_create(tables, max_block, stream=None, **kw) -> "Bank":
+    return Bank(tables, max_block, stream=stream, **kw)
+
+
+def spiir_process_block(bank: "Bank", x, z, stream=None) -> None:
+    bank.process_block(x, z, stream)
+
+
+def spiir_process_batch(requests, stream=None) -> None:
+    """requests: list of (bank, x, z) with torch device tensors."""
+    n = len(requests)
+    arr = (Request * max(n, 1))()
+    for i, (bank, x, z) in enumerate(requests):
+        _validate_io(bank, x, z)
+        arr[i] = Request(bank._h, x.data_ptr(), int(x.numel()), z.data_ptr(), int(z.stride(0)))
+    _check(load_library().spiir_process_batch(n, arr, _stream_handle(stream)), "spiir_process_batch")
+
+
+def spiir_profile_enable(on: bool = True) -> None:
+    _check(load_library().spiir_profile_enable(1 if on else 0), "spiir_profile_enable")
+
+
+def spiir_profile_read() -> dict:
+    d = ProfileData()
+    _check(load_library().spiir_profile_read(C.byref(d)), "spiir_profile_read")
+    names = ("stage", "filter", "upadd")
+    return {names[i]: {"launches": int(d.launches[i]), "ms": float(d.ms[i])} for i in range(3)}
+
+
+def _validate_io(bank, x, z):
+    import torch
+    if x.dtype != torch.float32 or not x.is_cuda or x.dim() != 1 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous 1-D float32 device tensor")
+    if z.dtype != torch.complex64 or not z.is_cuda or z.dim() != 2 or z.stride(1) != 1:
+        raise ValueError("z must be a 2-D complex64 device tensor with unit inner stride")
+    if z.shape[0] < bank.n_templates or z.shape[1] < x.numel():
+        raise ValueError("z is too small for this block")
+
+
+class Bank:
+    """One template bank bound to one input stream (owns its device memory)."""
+
+    def __init__(self, tables, max_block, stream=None, precision="fp32", carry_chunk=0,
+                 filters_per_lane=0, waves_per_group=0, device=0):
+        lib = load_library()
+        self._lib = lib
+        hold = _DescHolder(tables, max_block, precision, carry_chunk, filters_per_lane,
+                           waves_per_group, device)
+        self.n_templates = int(tables.n_filters.shape[0])
+        self.n_bands = int(tables.n_filters.shape[1])
+        self.max_block = int(max_block)
+        self.plan = spiir_plan(tables, max_block, precision=precision, carry_chunk=carry_chunk,
+                               filters_per_lane=filters_per_lane, waves_per_group=waves_per_group,
+                               device=device)
+        h = C.c_void_p()
+        s = _stream_handle(stream) if stream is not None else C.c_void_p(0)
+        _check(lib.spiir_create(C.byref(hold.desc), s, C.byref(h)), "spiir_create")
+        self._h = h.value
+
+    def process_block(self, x, z, stream=None) -> None:
+        _validate_io(self, x, z)
+        rc = self._lib.spiir_process_block(self._h, x.data_ptr(), int(x.numel()), z.data_ptr(),
+                                           int(z.stride(0)), _stream_handle(stream))
+        _check(rc, "spiir_process_block")
+
+    def process_raw(self, x_ptr: int, n: int, z_ptr: int, ldz: int, stream=None) -> int:
+        """Unchecked pointer form (returns the status code)."""
+        return self._lib.spiir_process_block(self._h, x_ptr, n, z_ptr, ldz, _stream_handle(stream))
+
+    @property
+    def samples_done(self) -> int:
+        v = C.c_int64()
+        _check(self._lib.spiir_samples_done(self._h, C.byref(v)), "spiir_samples_done")
+        return int(v.value)
+
+    def reset(self) -> None:
+        _check(self._lib.spiir_reset(self._h), "spiir_reset")
+
+    def state_size(self) -> int:
+        v = C.c_size_t()
+        _check(self._lib.spiir_state_size(self._h, C.byref(v)), "spiir_state_size")
+        return int(v.value)
+
+    def save_state(self, stream=None) -> bytes:
+        buf = C.create_string_buffer(self.state_size())
+        _check(self._lib.spiir_save_state(self._h, buf, _stream_handle(stream)), "spiir_save_state")
+        return buf.raw
+
+    def load_state(self, blob: bytes, stream=None) -> None:
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(self._lib.spiir_load_state(self._h, buf, _stream_handle(stream)), "spiir_load_state")
+
+    def status(self):
+        """(status code, per-template non-finite flags)."""
+        flags = np.zeros(self.n_templates, np.int32)
+        rc = self._lib.spiir_status(self._h, flags.ctypes.data_as(C.POINTER(C.c_int32)))
+        return rc, flags
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.spiir_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

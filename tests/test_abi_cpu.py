@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/spiir.h declares, validates descriptors and plans
+banks (lane packing, pieces, footprint) without touching a device."""
+import ctypes as C
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1702_02256_amd import spiir as S
+from paper_1702_02256_amd import workloads as W
+
+
+def _have_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.load_library()
+    declared = S.header_symbols()
+    assert "spiir_create" in declared and "spiir_process_block" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", S.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert set(declared) <= exported
+    # every exported spiir_ symbol is declared (no undocumented entry points)
+    assert {e for e in exported if e.startswith("spiir_")} <= set(declared)
+
+
+def test_strerror():
+    assert S.spiir_strerror(0) == "ok"
+    assert "invalid" in S.spiir_strerror(S.SPIIR_EINVAL)
+    assert "non-finite" in S.spiir_strerror(S.SPIIR_ENONFINITE)
+    assert S.spiir_strerror(12345) == "unknown status"
+
+
+def _small_multirate(T=3, H=3, seed=5):
+    nf = np.random.default_rng(seed).integers(1, 40, size=(T, H)).astype(np.int32)
+    return W.random_bank(seed, nf, 1024, W.multirate_dmax(1024, H))
+
+
+def test_plan_single_template_padding():
+    wl = W.config1()
+    p = S.spiir_plan(wl.bank, 4096, filters_per_lane=4, waves_per_group=4)
+    assert p["total_filters"] == 128
+    assert p["n_groups"] == 1 and p["n_pieces"] == 1
+    assert p["filter_slots"] == 4 * 256
+    assert p["carry_chunk"] == 32 and p["lanes_per_group"] == 256
+
+
+def test_plan_packs_segments_end_to_end():
+    wl = W.config2(n_templates=8, n_blocks=1)
+    p = S.spiir_plan(wl.bank, 2048, filters_per_lane=4, waves_per_group=4)
+    # 512 filters / 4 per lane = 128 lanes: two templates per 256-lane group
+    assert p["n_groups"] == 4 and p["n_pieces"] == 8
+    p8 = S.spiir_plan(wl.bank, 2048, filters_per_lane=8, waves_per_group=1)
+    assert p8["n_groups"] == 8 and p8["filter_slots"] == 8 * 512
+
+
+def test_plan_splits_segments_across_groups():
+    nf = np.array([[3000], [10]], np.int32)
+    tb = W.random_bank(3, nf, 4096, [100])
+    p = S.spiir_plan(tb, 4096, filters_per_lane=4, waves_per_group=4)
+    # 750 + 3 lanes over 256-lane groups -> 3 groups; template 0 is split in 3
+    assert p["n_groups"] == 3
+    assert p["n_pieces"] == 4
+    assert p["filter_slots"] >= 3010
+
+
+def test_plan_waste_is_bounded():
+    wl = W.config3(n_templates=64, n_blocks=1)
+    p = S.spiir_plan(wl.bank, 4096, filters_per_lane=4, waves_per_group=4)
+    segs = int((wl.bank.n_filters > 0).sum())
+    # at most F-1 padding slots per segment plus one partial group per band
+    assert p["filter_slots"] - p["total_filters"] <= segs * 3 + 7 * 4 * 256
+    assert p["n_pieces"] >= segs
+
+
+def test_footprint_matches_plan_and_scales():
+    a = _small_multirate(T=4)
+    b = _small_multirate(T=40)
+    fa, fb = S.spiir_footprint(a, 1024), S.spiir_footprint(b, 1024)
+    assert fa == S.spiir_plan(a, 1024)["footprint"]
+    assert fb > fa > 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_bands", 0), ("n_bands", 13), ("max_block", 0), ("max_block", 1023 + 2),
+    ("precision", 7), ("carry_chunk", 48), ("carry_chunk", 8), ("filters_per_lane", 3),
+    ("waves_per_group", 17), ("base_rate_hz", 0), ("n_templates", 0), ("device", -1),
+])
+def test_descriptor_validation(field, value):
+    tb = _small_multirate()
+    h = S._DescHolder(tb, 1024)
+    setattr(h.desc, field, value)
+    lib = S.load_library()
+    out = C.c_size_t()
+    assert lib.spiir_footprint(C.byref(h.desc), C.byref(out)) == S.SPIIR_EINVAL
+    bank = C.c_void_p(123)
+    assert lib.spiir_create(C.byref(h.desc), None, C.byref(bank)) == S.SPIIR_EINVAL
+    assert bank.value is None
+
+
+@pytest.mark.parametrize("bad", ["nan_a1", "neg_delay", "big_delay", "no_taps", "neg_count"])
+def test_table_validation(bad):
+    tb = _small_multirate()
+    if bad == "nan_a1":
+        tb.a1 = tb.a1.copy()
+        tb.a1[5] = np.nan
+    elif bad == "neg_delay":
+        tb.delay = tb.delay.copy()
+        tb.delay[2] = -1
+    elif bad == "big_delay":
+        tb.delay = tb.delay.copy()
+        tb.delay[2] = 16384
+    elif bad == "neg_count":
+        tb.n_filters = tb.n_filters.copy()
+        tb.n_filters[0, 0] = -1
+    h = S._DescHolder(tb, 1024)
+    if bad == "no_taps":
+        h.desc.n_taps_up = 0
+    out = C.c_size_t()
+    assert S.load_library().spiir_footprint(C.byref(h.desc), C.byref(out)) == S.SPIIR_EINVAL
+
+
+def test_process_calls_reject_null_bank():
+    lib = S.load_library()
+    assert lib.spiir_process_block(None, None, 16, None, 16, None) == S.SPIIR_EINVAL
+    assert lib.spiir_process_batch(0, None, None) == S.SPIIR_EINVAL
+    assert lib.spiir_destroy(None) == S.SPIIR_OK
+    assert lib.spiir_reset(None) == S.SPIIR_EINVAL
+    assert lib.spiir_status(None, None) == S.SPIIR_EINVAL
+
+
+@pytest.mark.skipif(_have_gpu(), reason="checks the no-device error path")
+def test_create_without_device_reports_device_error():
+    tb = _small_multirate()
+    h = S._DescHolder(tb, 1024)
+    bank = C.c_void_p()
+    rc = S.load_library().spiir_create(C.byref(h.desc), None, C.byref(bank))
+    assert rc == S.SPIIR_EDEVICE and bank.value is None

@@ -1,0 +1,331 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Metric (per template): max_k |z_gpu - z_ref| / max_k |z_ref| over the whole
+stream; the bar is 1e-5 for complex FP32 against the FP64 oracle.  Inputs are
+the seeded workloads; the oracle gets the FP64 stream, the GPU its FP32
+rounding.  Bitwise checks cover what must not depend on how the stream is cut
+or batched.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_02256_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def run_gpu(tables, x, blocks, max_block=None, **kw):
+    """Stream x through a fresh bank in the given block lengths -> complex128 [T, n]."""
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    T = tables.n_templates
+    n = int(sum(blocks))
+    assert n <= len(x)
+    bank = S.Bank(tables, max_block or max(blocks), **kw)
+    xt = torch.from_numpy(np.asarray(x[:n], np.float32)).cuda()
+    z = torch.zeros((T, n), dtype=torch.complex64, device="cuda")
+    pos = 0
+    for b in blocks:
+        bank.process_block(xt[pos:pos + b], z[:, pos:pos + b])
+        pos += b
+    torch.cuda.synchronize()
+    rc, flags = bank.status()
+    assert rc == 0, rc
+    out = z.cpu().numpy().astype(np.complex128)
+    bank.destroy()
+    return out
+
+
+def rel_err(zg, zr):
+    num = np.max(np.abs(zg - zr), axis=1)
+    den = np.maximum(np.max(np.abs(zr), axis=1), 1e-300)
+    return num / den
+
+
+def check(zg, zr, tol=TOL, label=""):
+    e = rel_err(zg, zr)
+    _say(f"{label}: max rel err {e.max():.3e} (median {np.median(e):.3e}, worst template {int(e.argmax())})")
+    assert np.all(np.isfinite(zg))
+    assert e.max() <= tol, (label, e.max())
+    return e
+
+
+# ---------------------------------------------------------------- the configs
+
+
+def test_config1_full():
+    wl = W.config1()
+    x = wl.stream()
+    _say("cfg1: 1 template x 128 filters, 4096 samples")
+    zg = run_gpu(wl.bank, x, [4096])
+    zr = oracle.run_stream(wl.bank, x)
+    check(zg, zr, label="cfg1")
+
+
+def test_config2_subset_all_blocks():
+    T = 16
+    wl = W.config2(n_templates=T, n_blocks=16)
+    x = wl.stream()
+    _say("cfg2 subset: 16 x 512 filters, 16 blocks of 2048 at 2048 Hz")
+    zg = run_gpu(wl.bank, x, [2048] * 16)
+    zr = oracle.run_stream(wl.bank, x)
+    check(zg, zr, label="cfg2-16")
+
+
+def test_config3_subset():
+    tsel = [0, 1, 777, 4095]
+    wl = W.config3(templates=tsel, n_blocks=4)
+    x = wl.stream()
+    _say("cfg3 subset: 4 templates x 7 bands, 4 blocks of 4096")
+    zg = run_gpu(wl.bank, x, [4096] * 4)
+    zr = oracle.run_stream(wl.bank, x)
+    check(zg, zr, label="cfg3-sub")
+
+
+def test_config4_subset_uneven():
+    tsel = list(range(24))
+    wl = W.config4(templates=tsel, n_blocks=2)
+    x = wl.stream()
+    _say("cfg4 subset: 24 uneven templates, 2 blocks of 4096")
+    zg = run_gpu(wl.bank, x, [4096, 4096])
+    zr = oracle.run_stream(wl.bank, x)
+    check(zg, zr, label="cfg4-sub")
+
+
+def test_config2_full_size_sampled():
+    """All 1024 templates for 16 s, in the benchmark's launch shape; the oracle
+    recomputes a random sample of templates (templates are independent)."""
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    wl = W.config2()
+    x = wl.stream()
+    _say("cfg2 full: 1024 x 512, 16 blocks, sampled check")
+    bank = S.Bank(wl.bank, 2048)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    z = torch.zeros((1024, 2048 * 16), dtype=torch.complex64, device="cuda")
+    for i in range(16):
+        bank.process_block(xt[i * 2048:(i + 1) * 2048], z[:, i * 2048:(i + 1) * 2048])
+    torch.cuda.synchronize()
+    sel = np.sort(np.random.default_rng(99).choice(1024, 12, replace=False))
+    zg = z[torch.as_tensor(sel, device="cuda")].cpu().numpy().astype(np.complex128)
+    zr = oracle.run_stream(wl.bank.subset(sel), x)
+    check(zg, zr, label="cfg2-full-sampled")
+    bank.destroy()
+
+
+def test_config3_full_size_sampled():
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    nb = 16
+    wl = W.config3(n_blocks=nb)
+    x = wl.stream()
+    _say("cfg3 full: 4096 templates x 7 bands, 16 blocks of 4096, sampled check")
+    bank = S.Bank(wl.bank, 4096)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    sel = np.sort(np.random.default_rng(98).choice(4096, 6, replace=False))
+    selt = torch.as_tensor(sel, device="cuda")
+    z = torch.zeros((4096, 4096), dtype=torch.complex64, device="cuda")
+    parts = []
+    for i in range(nb):
+        bank.process_block(xt[i * 4096:(i + 1) * 4096], z)
+        parts.append(z[selt].cpu().numpy().astype(np.complex128))
+    zg = np.concatenate(parts, axis=1)
+    zr = oracle.run_stream(wl.bank.subset(sel), x)
+    check(zg, zr, label="cfg3-full-sampled")
+    bank.destroy()
+
+
+# ---------------------------------------------------------------- streaming and edges
+
+
+def _mr_bank(seed=3, T=5, H=4, lo=1, hi=90, rate=1024):
+    nf = np.random.default_rng(seed).integers(lo, hi, size=(T, H)).astype(np.int32)
+    return W.random_bank(seed, nf, rate, W.multirate_dmax(rate, H))
+
+
+def test_block_split_is_bitwise_invariant():
+    tb = _mr_bank()
+    x = W.noise_stream(5, 4096)
+    a = run_gpu(tb, x, [4096], max_block=4096)
+    b = run_gpu(tb, x, [1024, 8, 504, 2048, 512], max_block=4096)
+    assert np.array_equal(a, b)
+
+
+def test_ragged_blocks_and_tails():
+    tb = _mr_bank(seed=4, T=3, H=3)
+    x = W.noise_stream(6, 3000)
+    blocks = [4, 12, 100, 1000, 4, 1880]
+    zg = run_gpu(tb, x, blocks, max_block=2048)
+    zr = oracle.run_stream(tb, x[:3000])
+    check(zg, zr, label="ragged")
+
+
+def test_long_blocks_split_inside_the_library():
+    """Blocks longer than one internal launch (4096) and delays beyond the block."""
+    tb = _mr_bank(seed=8, T=2, H=2, rate=4096)
+    x = W.noise_stream(7, 3 * 8192)
+    zg = run_gpu(tb, x, [8192, 8192, 8192], max_block=8192)
+    zr = oracle.run_stream(tb, x)
+    check(zg, zr, label="long-blocks")
+
+
+def test_edge_shapes():
+    # one filter; an empty band; a huge segment spanning several workgroups
+    nf = np.array([[1, 0, 2], [0, 0, 3], [2500, 0, 1], [7, 0, 0]], np.int32)
+    tb = W.random_bank(11, nf, 512, W.multirate_dmax(512, 3))
+    x = W.noise_stream(12, 2048)
+    zg = run_gpu(tb, x, [512] * 4)
+    zr = oracle.run_stream(tb, x)
+    check(zg, zr, label="edges")
+    assert np.all(zg[3] != 0)
+
+
+def test_large_delays_use_subblocks():
+    nf = np.array([[64], [64]], np.int32)
+    tb = W.random_bank(13, nf, 4096, [12000])
+    x = W.noise_stream(14, 4 * 4096)
+    zg = run_gpu(tb, x, [4096] * 4)
+    zr = oracle.run_stream(tb, x)
+    check(zg, zr, label="large-delays")
+
+
+@pytest.mark.parametrize("F,Wv", [(1, 1), (2, 2), (4, 4), (8, 4), (8, 8), (4, 8), (1, 8)])
+def test_lane_packing_variants(F, Wv):
+    tb = _mr_bank(seed=15, T=6, H=3, lo=1, hi=300)
+    x = W.noise_stream(16, 2048)
+    zg = run_gpu(tb, x, [1024, 1024], filters_per_lane=F, waves_per_group=Wv)
+    zr = oracle.run_stream(tb, x)
+    check(zg, zr, label=f"F{F}W{Wv}")
+
+
+@pytest.mark.parametrize("C", [16, 64, 256])
+def test_carry_chunk_variants(C):
+    wl = W.config1()
+    x = wl.stream()
+    zg = run_gpu(wl.bank, x, [4096], carry_chunk=C)
+    zr = oracle.run_stream(wl.bank, x)
+    check(zg, zr, label=f"C{C}")
+
+
+def test_compensated_mode():
+    T = 8
+    wl = W.config2(n_templates=T, n_blocks=4)
+    x = wl.stream()
+    zr = oracle.run_stream(wl.bank, x[:8192])
+    zp = run_gpu(wl.bank, x, [2048] * 4, precision="fp32")
+    zc = run_gpu(wl.bank, x, [2048] * 4, precision="fp32_compensated")
+    check(zp, zr, label="plain")
+    check(zc, zr, label="compensated")
+
+
+def test_zero_padding_invariance():
+    nf = np.array([[20], [33]], np.int32)
+    tb = W.random_bank(17, nf, 1024, [200])
+    pad = 11
+    off = tb.offsets()
+    a1, b0, d = [], [], []
+    for t in range(2):
+        s, m = off[t, 0], nf[t, 0]
+        a1 += [tb.a1[s:s + m], np.zeros(pad)]
+        b0 += [tb.b0[s:s + m], np.zeros(pad)]
+        d += [tb.delay[s:s + m], np.arange(pad, dtype=np.int32)]
+    tp = W.BankTables(1024, nf + pad, np.concatenate(a1), np.concatenate(b0), np.concatenate(d))
+    x = W.noise_stream(18, 2048)
+    za = run_gpu(tb, x, [2048])
+    zb = run_gpu(tp, x, [2048])
+    check(zb, za, tol=1e-6, label="zero-pad")
+
+
+# ---------------------------------------------------------------- ABI behaviour on the device
+
+
+def test_batch_equals_alone_bitwise():
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    tabs = [_mr_bank(seed=20 + i, T=4 + i, H=3) for i in range(3)]
+    xs = [W.noise_stream(30 + i, 2048) for i in range(3)]
+    lens = [1024, 512, 2048]
+    alone = [run_gpu(tabs[i], xs[i], [lens[i]], max_block=2048) for i in range(3)]
+    banks = [S.Bank(t, 2048) for t in tabs]
+    xt = [torch.from_numpy(xs[i][:lens[i]].astype(np.float32)).cuda() for i in range(3)]
+    zt = [torch.zeros((tabs[i].n_templates, lens[i]), dtype=torch.complex64, device="cuda")
+          for i in range(3)]
+    S.spiir_process_batch([(banks[i], xt[i], zt[i]) for i in range(3)])
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert np.array_equal(zt[i].cpu().numpy().astype(np.complex128), alone[i]), i
+        banks[i].destroy()
+
+
+def test_save_load_roundtrip_bitwise():
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    tb = _mr_bank(seed=40, T=3, H=3)
+    x = W.noise_stream(41, 4096)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    bank = S.Bank(tb, 2048)
+    z = torch.zeros((3, 2048), dtype=torch.complex64, device="cuda")
+    bank.process_block(xt[:2048], z)
+    blob = bank.save_state()
+    z1 = torch.zeros_like(z)
+    bank.process_block(xt[2048:], z1)
+    bank.load_state(blob)
+    assert bank.samples_done == 2048
+    z2 = torch.zeros_like(z)
+    bank.process_block(xt[2048:], z2)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z2)
+    bank.reset()
+    assert bank.samples_done == 0
+    z3 = torch.zeros_like(z)
+    bank.process_block(xt[:2048], z3)
+    torch.cuda.synchronize()
+    assert torch.equal(z3, z)
+    bank.destroy()
+
+
+def test_invalid_block_leaves_state_unchanged():
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    tb = _mr_bank(seed=50, T=2, H=3)
+    x = W.noise_stream(51, 1024)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    bank = S.Bank(tb, 1024)
+    z = torch.zeros((2, 1024), dtype=torch.complex64, device="cuda")
+    assert bank.process_raw(xt.data_ptr(), 6, z.data_ptr(), 1024) == S.SPIIR_EINVAL
+    assert bank.process_raw(xt.data_ptr(), 2048, z.data_ptr(), 4096) == S.SPIIR_EINVAL
+    assert bank.process_raw(xt.data_ptr(), 512, z.data_ptr(), 100) == S.SPIIR_EINVAL
+    assert bank.samples_done == 0
+    bank.process_block(xt, z)
+    torch.cuda.synchronize()
+    ref = run_gpu(tb, x, [1024])
+    assert np.array_equal(z.cpu().numpy().astype(np.complex128), ref)
+    bank.destroy()
+
+
+def test_nonfinite_input_is_flagged_and_reset_clears():
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    tb = _mr_bank(seed=60, T=3, H=1)
+    x = W.noise_stream(61, 1024).astype(np.float32)
+    x[100] = np.nan
+    bank = S.Bank(tb, 1024)
+    z = torch.zeros((3, 1024), dtype=torch.complex64, device="cuda")
+    bank.process_block(torch.from_numpy(x).cuda(), z)
+    rc, flags = bank.status()
+    assert rc == S.SPIIR_ENONFINITE and flags.all()
+    bank.reset()
+    rc, flags = bank.status()
+    assert rc == 0 and not flags.any()
+    bank.destroy()
