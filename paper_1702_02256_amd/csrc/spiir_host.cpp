@@ -20,10 +20,8 @@ namespace {
 constexpr int kDefaultF = 4;
 constexpr int kDefaultW = 4;
 constexpr int kDefaultC = 32;
-constexpr int kInner = 4096;        // base-rate samples per launch sequence
-constexpr int kXcapDefault = 8192;  // LDS window, floats
-constexpr int kXcapMax = 24576;
-constexpr int kXcapSlack = 512;     // window samples beyond the largest delay
+constexpr int kSubBlock = 512;      // samples per LDS window restage
+constexpr int kXcapMax = 24576;     // LDS window, floats
 constexpr int kMaxLds = 160 * 1024;
 constexpr uint32_t kStateMagic = 0x53504952u;  // "SPIR"
 constexpr uint32_t kStateVersion = 1;
@@ -44,6 +42,7 @@ struct Plan {
     int64_t total_filters = 0, n_slots = 0, zw_elems = 0, ring_total = 0;
     std::vector<int> maxd_band, S, ring_mask;
     std::vector<int64_t> ring_off;
+    std::vector<int64_t> zstride;   // workspace row per piece, per band (even length)
     std::vector<int> band_wg0;
     std::vector<WgDesc> wg;
     std::vector<PieceDesc> piece;
@@ -114,7 +113,7 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
     p.C = d->carry_chunk ? d->carry_chunk : kDefaultC;
     p.precision = d->precision;
     p.max_block = d->max_block;
-    p.mb_inner = std::min(d->max_block, kInner);
+    p.mb_inner = std::min(d->max_block, kInnerBlock);
     p.td = p.H > 1 ? d->n_taps_down : 1;
     p.tu = p.H > 1 ? d->n_taps_up : 1;
     p.hu_len = (p.tu + 1) / 2;
@@ -134,20 +133,22 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
             for (int l = 0; l < d->n_filters[t * H + h]; ++l)
                 p.maxd_band[h] = std::max(p.maxd_band[h], (int)d->delay[moff[t * H + h] + l]);
 
-    // LDS window: maxd + S floats, S a multiple of kTile (or the whole band block)
-    int X = kXcapDefault;
+    // LDS window: maxd + S floats per band, S = min(block, kSubBlock); the
+    // window is restaged every S samples
+    int X = 0;
     for (int h = 0; h < H; ++h)
-        X = std::max(X, p.maxd_band[h] + std::min(kXcapSlack, p.mb_inner >> h) + kTile);
+        X = std::max(X, p.maxd_band[h] + std::min(kSubBlock, p.mb_inner >> h));
     X = (X + 3) & ~3;
     if (X > kXcapMax) return SPIIR_EINVAL;
     p.xcap = X;
     p.S.assign(H, 0);
+    p.zstride.assign(H, 0);
+    for (int h = 0; h < H; ++h) p.zstride[h] = (int64_t)(((p.mb_inner >> h) + 1) & ~1);
     p.ring_mask.assign(H, 0);
     p.ring_off.assign(H, 0);
     for (int h = 0; h < H; ++h) {
         const int nh = p.mb_inner >> h;
-        const int room = ((X - p.maxd_band[h]) / kTile) * kTile;
-        p.S[h] = std::max(1, std::min(nh, room));
+        p.S[h] = std::min(kSubBlock, nh);
         const int64_t P = next_pow2((int64_t)nh + std::max(p.maxd_band[h], p.td) + 1);
         p.ring_mask[h] = (int)(P - 1);
         p.ring_off[h] = p.ring_total;
@@ -217,22 +218,81 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
         open_wg();
     };
 
+    // Bank-aware placement.  A lane's x read for slot f hits LDS bank
+    // (maxd - d + k) mod 32, so within one half-wave and slot the lanes
+    // conflict exactly when their delays agree mod 32.  Each segment's filters
+    // are dealt to its (lane, slot) positions greedily, picking for every
+    // position a delay residue that is least used so far in that row.
+    constexpr int kBanks = 32;
+    const int halves = L / 32;
+    using Counts = std::vector<uint16_t>;  // [F][halves][kBanks]
+    auto fresh_counts = [&]() { return Counts((size_t)F * halves * kBanks, 0); };
+    Counts cur_counts = fresh_counts();
+
     open_wg();
     for (int h = 0; h < H; ++h) {
         p.band_wg0[h] = (int)p.wg.size();
-        const int64_t zstride = p.mb_inner >> h;
+        const int64_t zstride = p.zstride[h];
         for (int t = 0; t < T; ++t) {
             const int M = d->n_filters[t * H + h];
             if (M == 0) continue;
-            const int nl = (M + F - 1) / F;
+            // an even number of lanes: lane pairs never straddle a run boundary
+            const int nl = (((M + F - 1) / F) + 1) & ~1;
+            const int64_t base = moff[t * H + h];
+
+            // where the segment's lanes will land (mirrors the placement below)
+            std::vector<int> lane_wg(nl), lane_pos(nl);
+            {
+                int lanes = cur.lanes;
+                int pieces = cur.lanes ? cur.lane_piece.back() - cur.lane_piece.front() + 1 : 0;
+                int wgid = 0, placed = 0;
+                while (placed < nl) {
+                    if (lanes == L || pieces >= kMaxPiecesPerGroup) {
+                        ++wgid;
+                        lanes = 0;
+                        pieces = 0;
+                    }
+                    const int take = std::min(nl - placed, L - lanes);
+                    ++pieces;
+                    for (int i = 0; i < take; ++i) {
+                        lane_wg[placed + i] = wgid;
+                        lane_pos[placed + i] = lanes + i;
+                    }
+                    lanes += take;
+                    placed += take;
+                }
+            }
+            std::vector<Counts> counts(1, cur_counts);
+            for (int i = 0; i < nl; ++i)
+                while ((int)counts.size() <= lane_wg[i]) counts.push_back(fresh_counts());
+
+            std::vector<std::vector<int>> bucket(kBanks);
+            for (int j = M - 1; j >= 0; --j) bucket[d->delay[base + j] % kBanks].push_back(j);
+            std::vector<int> assign((size_t)nl * F, -1);
+            for (int f = 0; f < F; ++f)
+                for (int i = 0; i < nl; ++i) {
+                    if (i * F + f >= M) continue;  // padding positions: the tail of the last lane
+                    uint16_t* row = counts[lane_wg[i]].data() +
+                                    ((size_t)f * halves + lane_pos[i] / 32) * kBanks;
+                    int best = -1;
+                    for (int r = 0; r < kBanks; ++r)
+                        if (!bucket[r].empty() && (best < 0 || row[r] < row[best])) best = r;
+                    assign[(size_t)i * F + f] = bucket[best].back();
+                    bucket[best].pop_back();
+                    row[best]++;
+                }
+
             SegDesc& sg = p.seg[(size_t)t * H + h];
             sg.zoff = p.zw_elems;
             sg.npiece = 0;
-            int placed = 0;
+            int placed = 0, wg_seen = 0;
             while (placed < nl) {
                 const int cur_pieces =
                     cur.lanes ? cur.lane_piece.back() - cur.lane_piece.front() + 1 : 0;
-                if (cur.lanes == L || cur_pieces >= kMaxPiecesPerGroup) close_wg(h);
+                if (cur.lanes == L || cur_pieces >= kMaxPiecesPerGroup) {
+                    close_wg(h);
+                    ++wg_seen;
+                }
                 const int take = std::min(nl - placed, L - cur.lanes);
                 PieceDesc pc{};
                 pc.zoff = p.zw_elems;
@@ -244,9 +304,9 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
                 for (int i = 0; i < take; ++i) {
                     const int lane = cur.lanes + i;
                     for (int f = 0; f < F; ++f) {
-                        const int j = (placed + i) * F + f;
-                        if (j >= M) break;
-                        const int64_t src = moff[t * H + h] + j;
+                        const int j = assign[(size_t)(placed + i) * F + f];
+                        if (j < 0) continue;
+                        const int64_t src = base + j;
                         wslot_src[(size_t)f * L + lane] = src;
                         wslot_d[(size_t)f * L + lane] = d->delay[src];
                     }
@@ -255,12 +315,17 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
                 cur.lanes += take;
                 placed += take;
             }
+            cur_counts = counts[wg_seen];
         }
         close_wg(h);
+        cur_counts = fresh_counts();
     }
     p.band_wg0[H] = (int)p.wg.size();
+    // the kernel adds lane pairs before the run reduction: runs must end on odd lanes
+    for (size_t i = 0; i < p.lane_meta.size(); ++i)
+        if ((p.lane_meta[i] & 0xffff) != kSlotNone && (i & 1) == 0) return SPIIR_EINVAL;
 
-    p.lds_filter = p.xcap * 4 + L * (kTile + 1) * 8 + kTile * p.nrun_max * 8 + p.npiece_max * 8 +
+    p.lds_filter = p.xcap * 4 + (L / 2) * (kTile + 1) * 8 + 2 * kTile * p.nrun_max * 8 + p.npiece_max * 8 +
                    L * 4 + p.npiece_max * 8;
     p.lds_stage = ((p.td - 1) + p.mb_inner + (p.td - 1) + p.mb_inner / 2 + p.td) * 4;
     p.lds_up = 2 * (p.hu_len + p.mb_inner / 2) * 8 + p.tu * 4;
@@ -528,6 +593,7 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
         bd.S[h] = p.S[h];
         bd.ring_mask[h] = p.ring_mask[h];
         bd.ring_off[h] = p.ring_off[h];
+        bd.zstride[h] = p.zstride[h];
     }
     for (int h = 0; h <= p.H; ++h) bd.band_wg0[h] = p.band_wg0[h];
     bd.wg = b->wg;
@@ -613,7 +679,7 @@ int spiir_process_batch(int32_t n_req, const spiir_request* req, void* stream)
     int64_t maxn = 0;
     for (int r = 0; r < n_req; ++r) maxn = std::max<int64_t>(maxn, req[r].n);
     int F = req[0].bank->plan.F, L = req[0].bank->plan.L, prec = req[0].bank->plan.precision;
-    for (int64_t c0 = 0; c0 < maxn && e == hipSuccess; c0 += kInner) {
+    for (int64_t c0 = 0; c0 < maxn && e == hipSuccess; c0 += kInnerBlock) {
         LaunchArgs A;
         std::memset(&A, 0, sizeof(A));
         int rmap[SPIIR_MAX_BATCH];
@@ -631,7 +697,7 @@ int spiir_process_batch(int32_t n_req, const spiir_request* req, void* stream)
             ra.z = reinterpret_cast<c32*>(q.z_dev) + c0;
             ra.ldz = q.ldz;
             ra.s0 = b->done;
-            ra.n = (int32_t)std::min<int64_t>(kInner, q.n - c0);
+            ra.n = (int32_t)std::min<int64_t>(kInnerBlock, q.n - c0);
             ra.H = p.H;
             lds_f = std::max(lds_f, p.lds_filter);
             lds_s = std::max(lds_s, p.lds_stage);

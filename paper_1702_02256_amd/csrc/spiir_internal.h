@@ -19,6 +19,7 @@
 namespace spiir {
 
 constexpr int kTile = 16;        // samples per reduction tile (R)
+constexpr int kInnerBlock = 4096; // base-rate samples one launch sequence covers
 constexpr int kRunLanes = 16;    // lanes per level-1 run group
 constexpr int kMaxReq = SPIIR_MAX_BATCH;
 constexpr int kMaxBands = SPIIR_MAX_BANDS;
@@ -74,6 +75,7 @@ struct BankDev {
     int32_t S[kMaxBands];           // window sub-block length per band
     int32_t ring_mask[kMaxBands];   // ring size - 1 per band (power of two)
     int64_t ring_off[kMaxBands];    // band ring offset in `rings`
+    int64_t zstride[kMaxBands];     // workspace row length per band (even)
     int32_t band_wg0[kMaxBands + 1];
     const WgDesc* wg;
     const PieceDesc* piece;

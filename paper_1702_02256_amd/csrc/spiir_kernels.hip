@@ -25,9 +25,10 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
 
 // ---------------------------------------------------------------------------
 // Input staging and the downsample cascade (one workgroup per request).
+constexpr int kStageThreads = 1024;
 // LDS: cur [td-1 + max_block] | nxt [td-1 + max_block/2] | taps [td]
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_stage(LaunchArgs args)
+__global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
 {
     extern __shared__ float sm[];
     const ReqArg& q = args.req[blockIdx.x];
@@ -74,9 +75,15 @@ __global__ void __launch_bounds__(256) k_stage(LaunchArgs args)
 
 // ---------------------------------------------------------------------------
 // The filter bank.
-// LDS: xw [xcap] | pbuf [L][kTile+1] c32 | l2 [kTile][nrun_max] c32 |
+// LDS: xw [xcap] | pbuf [L/2][kTile+1] c32 | l2 2 x [kTile][nrun_max] c32 |
 //      pzoff [npiece_max] i64 | lmeta [L] i32 | prun [npiece_max] int2
 // ---------------------------------------------------------------------------
+// value of the other lane of the pair (lane ^ 1), via DPP quad_perm [1,0,3,2]
+__device__ __forceinline__ float pair_swap(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
 template <int F>
 __device__ __forceinline__ void lane_sum(float (&vr)[F], float (&vi)[F])
 {
@@ -88,6 +95,46 @@ __device__ __forceinline__ void lane_sum(float (&vr)[F], float (&vi)[F])
             vr[i] += vr[i + s];
             vi[i] += vi[i + s];
         }
+}
+
+// NSTEPS samples of Eq. 7 for the lane's F filters (NSTEPS = 0: `cnt` samples,
+// not unrolled).  Each sample's lane sum is combined with the other lane of the
+// pair and stored (one component per lane); the restrict-qualified pointer tells
+// the compiler that these stores never alias the x window, so the loads of
+// later samples can be issued ahead of them.
+template <int F, int NSTEPS>
+__device__ __forceinline__ void tile_steps(const float* const (&xb)[F], float* __restrict__ pcol,
+                                           bool even_lane, const float (&ar)[F],
+                                           const float (&ai)[F], const float (&br)[F],
+                                           const float (&bi)[F], float (&yr)[F], float (&yi)[F],
+                                           int cnt = NSTEPS)
+{
+    const float* __restrict__ x0[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) x0[f] = xb[f];
+    auto step = [&](int j) {
+        float tr[F], ti[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const float xv = x0[f][j];
+            const float pr = br[f] * xv, pi = bi[f] * xv;
+            const float nr = fmaf(ar[f], yr[f], fmaf(-ai[f], yi[f], pr));
+            const float ni = fmaf(ar[f], yi[f], fmaf(ai[f], yr[f], pi));
+            yr[f] = nr; yi[f] = ni;
+            tr[f] = nr; ti[f] = ni;
+        }
+        lane_sum<F>(tr, ti);
+        // even lane: re_even + re_odd; odd lane: im_odd + im_even
+        const float mine = even_lane ? tr[0] : ti[0];
+        const float send = even_lane ? ti[0] : tr[0];
+        pcol[2 * j] = mine + pair_swap(send);
+    };
+    if constexpr (NSTEPS > 0) {
+#pragma unroll
+        for (int j = 0; j < NSTEPS; ++j) step(j);
+    } else {
+        for (int j = 0; j < cnt; ++j) step(j);
+    }
 }
 
 template <int F, bool COMP>
@@ -114,8 +161,8 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
 
     float* xw = sm;
     c32* pbuf = reinterpret_cast<c32*>(xw + bd->xcap);
-    c32* l2 = pbuf + L * (kTile + 1);
-    long long* pzoff = reinterpret_cast<long long*>(l2 + kTile * nrun);
+    c32* l2buf = pbuf + (L / 2) * (kTile + 1);  // two tile buffers of run sums
+    long long* pzoff = reinterpret_cast<long long*>(l2buf + 2 * kTile * nrun);
     int* lmeta = reinterpret_cast<int*>(pzoff + bd->npiece_max);
     int2* prun = reinterpret_cast<int2*>(lmeta + L);
 
@@ -147,8 +194,8 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
     unsigned endmask = 0;
     int slot0 = -1;
 #pragma unroll
-    for (int i = 0; i < kRunLanes; ++i) {
-        const int sl = lmeta[q1 * kRunLanes + i] & 0xffff;
+    for (int i = 0; i < kRunLanes / 2; ++i) {
+        const int sl = lmeta[q1 * kRunLanes + 2 * i + 1] & 0xffff;
         if (sl != kSlotNone) {
             endmask |= 1u << i;
             if (slot0 < 0) slot0 = sl;
@@ -158,7 +205,13 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
     const int S = bd->S[h];
     const float* ring = bd->rings + bd->ring_off[h];
     const int64_t mk = bd->ring_mask[h];
-    c32* prow = pbuf + tid * (kTile + 1);
+    // Lanes come in pairs of one run (segments span an even number of lanes).
+    // The pair sum of sample j is entry e = lane/2 of row j: pbuf[e*(kTile+1) + j],
+    // the even lane storing its real part and the odd lane its imaginary part.
+    const int pe = tid >> 1;
+    const bool even_lane = (tid & 1) == 0;
+    float* pcol = reinterpret_cast<float*>(pbuf + pe * (kTile + 1)) + (tid & 1);
+    int parity = 0;
 
     for (int kb = 0; kb < nh; kb += S) {
         const int sub = min(S, nh - kb);
@@ -177,44 +230,10 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
 #pragma unroll
             for (int f = 0; f < F; ++f) xb[f] = xw + off[f] + (k - kb);
 
-            if (cnt == kTile) {
-                // partials stay in registers until the tile ends, so no LDS store
-                // sits between the x loads of consecutive samples
-                float zr[kTile], zi[kTile];
-#pragma unroll
-                for (int j = 0; j < kTile; ++j) {
-                    float tr[F], ti[F];
-#pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        const float xv = xb[f][j];
-                        const float pr = br[f] * xv, pi = bi[f] * xv;
-                        const float nr = fmaf(ar[f], yr[f], fmaf(-ai[f], yi[f], pr));
-                        const float ni = fmaf(ar[f], yi[f], fmaf(ai[f], yr[f], pi));
-                        yr[f] = nr; yi[f] = ni;
-                        tr[f] = nr; ti[f] = ni;
-                    }
-                    lane_sum<F>(tr, ti);
-                    zr[j] = tr[0];
-                    zi[j] = ti[0];
-                }
-#pragma unroll
-                for (int j = 0; j < kTile; ++j) prow[j] = c32{zr[j], zi[j]};
-            } else {
-                for (int j = 0; j < cnt; ++j) {
-                    float tr[F], ti[F];
-#pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        const float xv = xb[f][j];
-                        const float pr = br[f] * xv, pi = bi[f] * xv;
-                        const float nr = fmaf(ar[f], yr[f], fmaf(-ai[f], yi[f], pr));
-                        const float ni = fmaf(ar[f], yi[f], fmaf(ai[f], yr[f], pi));
-                        yr[f] = nr; yi[f] = ni;
-                        tr[f] = nr; ti[f] = ni;
-                    }
-                    lane_sum<F>(tr, ti);
-                    prow[j] = c32{tr[0], ti[0]};
-                }
-            }
+            if (cnt == kTile)
+                tile_steps<F, kTile>(xb, pcol, even_lane, ar, ai, br, bi, yr, yi);
+            else
+                tile_steps<F, 0>(xb, pcol, even_lane, ar, ai, br, bi, yr, yi, cnt);
 
             // carry correction after the last sample of an absolute chunk of C samples
             if (((kabs + cnt) & cmask) == 0) {
@@ -227,30 +246,65 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
                 }
             }
 
-            __syncthreads();
+            // Level 1 reads only partials written by the thread's own wave (its
+            // 16-lane group lies inside the wave), so a wave-local sync suffices.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            c32* l2 = l2buf + parity * (kTile * nrun);
             // level 1: each thread sums one sample row over the runs of a 16-lane group
+            // (all 16 partials are loaded before any run result is stored)
             if (j1 < cnt) {
-                const c32* col = pbuf + (q1 * kRunLanes) * (kTile + 1) + j1;
-                c32* out = l2 + j1 * nrun;
-                int slot = slot0;
-                float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
+                constexpr int kPairs = kRunLanes / 2;
+                const int e0 = q1 * kPairs;
+                const c32* grp = pbuf + e0 * (kTile + 1) + j1;
+                c32 v[kPairs];
 #pragma unroll
-                for (int i = 0; i < kRunLanes; ++i) {
-                    const c32 v = col[i * (kTile + 1)];
-                    if (COMP) {
-                        float e1, e2;
-                        two_sum(accr, v.x, accr, e1);
-                        two_sum(acci, v.y, acci, e2);
-                        er += e1;
-                        ei += e2;
-                    } else {
-                        accr += v.x;
-                        acci += v.y;
+                for (int i = 0; i < kPairs; ++i) v[i] = grp[i * (kTile + 1)];
+                c32* out = l2 + j1 * nrun;
+                if (endmask == (1u << (kPairs - 1))) {
+                    // the whole group is one run
+                    float accr = v[0].x, acci = v[0].y, er = 0.0f, ei = 0.0f;
+#pragma unroll
+                    for (int i = 1; i < kPairs; ++i) {
+                        if (COMP) {
+                            float e1, e2;
+                            two_sum(accr, v[i].x, accr, e1);
+                            two_sum(acci, v[i].y, acci, e2);
+                            er += e1;
+                            ei += e2;
+                        } else {
+                            accr += v[i].x;
+                            acci += v[i].y;
+                        }
                     }
-                    if (endmask & (1u << i)) {
-                        out[slot] = c32{accr + er, acci + ei};
-                        ++slot;
-                        accr = 0.0f; acci = 0.0f; er = 0.0f; ei = 0.0f;
+                    out[slot0] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
+                } else {
+                    int slot = slot0;
+                    float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
+                    bool fresh = true;
+#pragma unroll
+                    for (int i = 0; i < kPairs; ++i) {
+                        if (fresh) {
+                            accr = v[i].x;
+                            acci = v[i].y;
+                            er = 0.0f;
+                            ei = 0.0f;
+                        } else if (COMP) {
+                            float e1, e2;
+                            two_sum(accr, v[i].x, accr, e1);
+                            two_sum(acci, v[i].y, acci, e2);
+                            er += e1;
+                            ei += e2;
+                        } else {
+                            accr += v[i].x;
+                            acci += v[i].y;
+                        }
+                        fresh = (endmask >> i) & 1u;
+                        if (fresh) {
+                            out[slot] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
+                            ++slot;
+                        }
                     }
                 }
             }
@@ -276,9 +330,10 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
                             acci += v.y;
                         }
                     }
-                    bd->zw[pzoff[p] + k + j] = c32{accr + er, acci + ei};
+                    bd->zw[pzoff[p] + k + j] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
                 }
             }
+            parity ^= 1;
             k += cnt;
         }
     }
@@ -298,10 +353,52 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
 }
 
 // ---------------------------------------------------------------------------
-// Upsample-and-add chain, one workgroup per (request, template).
+// Upsample-and-add chain, one workgroup of kUpThreads per (request, template).
+// Every band's piece sums are fetched into registers first (one burst of
+// independent loads), then the chain runs from LDS, lowest band first.  A
+// thread owns low-rate samples m = tid + kUpThreads*i of acc_{h+1} and writes
+// both polyphase outputs acc_h[2m] and acc_h[2m+1] from the same window.
 // LDS: e0 [hu_len + max_block/2] c32 | e1 [same] | taps [tu]
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_upadd(LaunchArgs args)
+constexpr int kUpThreads = 256;
+
+// low-rate samples per thread for the boundary between band h and h+1
+__host__ __device__ constexpr int up_slots(int h)
+{
+    return (kInnerBlock >> (h + 1)) / kUpThreads > 1 ? (kInnerBlock >> (h + 1)) / kUpThreads : 1;
+}
+__host__ __device__ constexpr int up_slot_base(int h)
+{
+    return h == 0 ? 0 : up_slot_base(h - 1) + up_slots(h - 1);
+}
+constexpr int kUpSlotsTotal = up_slot_base(kMaxBands - 1);
+
+__device__ __forceinline__ c32 piece_sum(const c32* zw, const SegDesc& sg, int64_t stride, int k)
+{
+    float vr = 0.0f, vi = 0.0f;
+    for (int p = 0; p < sg.npiece; ++p) {
+        const c32 u = zw[sg.zoff + p * stride + k];
+        vr += u.x;
+        vi += u.y;
+    }
+    return c32{vr, vi};
+}
+
+__device__ __forceinline__ float4 piece_sum2(const c32* zw, const SegDesc& sg, int64_t stride,
+                                             int k)
+{
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int p = 0; p < sg.npiece; ++p) {
+        const float4 u = *reinterpret_cast<const float4*>(zw + sg.zoff + p * stride + k);
+        v.x += u.x;
+        v.y += u.y;
+        v.z += u.z;
+        v.w += u.w;
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
 {
     extern __shared__ float sm[];
     const int bid = blockIdx.x;
@@ -310,48 +407,89 @@ __global__ void __launch_bounds__(256) k_upadd(LaunchArgs args)
     const ReqArg& q = args.req[r];
     const BankDev* bd = q.bd;
     const int t = bid - args.tcum[r];
+    const int tid = threadIdx.x;
     const int H = bd->H, n = q.n, HU = bd->hu_len, tu = bd->tu, MB = bd->max_block;
+    const SegDesc* seg = bd->seg + (int64_t)t * H;
+    c32* zrow = q.z + (int64_t)t * q.ldz;
+
+    if (H == 1) {
+        const SegDesc sg = seg[0];
+        for (int k = tid; k < n; k += kUpThreads) zrow[k] = piece_sum(bd->zw, sg, bd->zstride[0], k);
+        return;
+    }
+
     const int ext = HU + MB / 2;
     c32* cur = reinterpret_cast<c32*>(sm);
     c32* nxt = cur + ext;
     float* hu = reinterpret_cast<float*>(nxt + ext);
-    for (int i = threadIdx.x; i < tu; i += blockDim.x) hu[i] = bd->hu[i];
-    __syncthreads();
+    for (int i = tid; i < tu; i += kUpThreads) hu[i] = bd->hu[i];
 
-    for (int h = H - 1; h >= 0; --h) {
-        const int nh = n >> h;
-        const SegDesc sg = bd->seg[(int64_t)t * H + h];
-        const int64_t stride = (int64_t)(MB >> h);
+    // lowest band: acc_{H-1} = z_{H-1}, placed after its history
+    {
+        const int h = H - 1, nh = n >> h;
+        const SegDesc sg = seg[h];
         c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
-        if (h > 0)
-            for (int i = threadIdx.x; i < HU; i += blockDim.x) nxt[i] = hist[i];
-        for (int k = threadIdx.x; k < nh; k += blockDim.x) {
-            float vr = 0.0f, vi = 0.0f;
-            for (int p = 0; p < sg.npiece; ++p) {
-                const c32 u = bd->zw[sg.zoff + p * stride + k];
-                vr += u.x;
-                vi += u.y;
-            }
-            if (h < H - 1) {
-                // acc_h[k] += sum_i h_u[ph + 2i] * acc_{h+1}[(k >> 1) - i]
-                const int ph = k & 1;
-                const c32* src = cur + HU + (k >> 1);
-                for (int i = 0; ph + 2 * i < tu; ++i) {
-                    const float c = hu[ph + 2 * i];
-                    const c32 u = src[-i];
-                    vr = fmaf(c, u.x, vr);
-                    vi = fmaf(c, u.y, vi);
+        for (int i = tid; i < HU; i += kUpThreads) cur[i] = hist[i];
+        for (int k = tid; k < nh; k += kUpThreads) cur[HU + k] = piece_sum(bd->zw, sg, bd->zstride[h], k);
+        __syncthreads();
+        for (int i = tid; i < HU; i += kUpThreads) hist[i] = cur[nh + i];
+    }
+
+    // every other band's own output, both phases per low-rate sample
+    float4 pv[kUpSlotsTotal];
+#pragma unroll
+    for (int h = 0; h < kMaxBands - 1; ++h) {
+#pragma unroll
+        for (int i = 0; i < up_slots(h); ++i) {
+            pv[up_slot_base(h) + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const int m = tid + kUpThreads * i;
+            if (h < H - 1 && m < (n >> (h + 1)))
+                pv[up_slot_base(h) + i] = piece_sum2(bd->zw, seg[h], bd->zstride[h], 2 * m);
+        }
+    }
+
+    const int ne = HU, no = tu / 2;  // even and odd polyphase tap counts
+#pragma unroll
+    for (int h = kMaxBands - 2; h >= 0; --h) {
+        if (h <= H - 2) {
+            const int nh = n >> h, nlo = n >> (h + 1);
+            c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
+            if (h > 0)
+                for (int i = tid; i < HU; i += kUpThreads) nxt[i] = hist[i];
+#pragma unroll
+            for (int i = 0; i < up_slots(h); ++i) {
+                const int m = tid + kUpThreads * i;
+                if (m < nlo) {
+                    const float4 v = pv[up_slot_base(h) + i];
+                    float er = v.x, ei = v.y, orr = v.z, oi = v.w;
+                    const c32* a = cur + HU + m;
+                    for (int j = 0; j < ne; ++j) {
+                        const c32 u = a[-j];
+                        const float ce = hu[2 * j];
+                        er = fmaf(ce, u.x, er);
+                        ei = fmaf(ce, u.y, ei);
+                        if (j < no) {
+                            const float co = hu[2 * j + 1];
+                            orr = fmaf(co, u.x, orr);
+                            oi = fmaf(co, u.y, oi);
+                        }
+                    }
+                    if (h == 0) {
+                        zrow[2 * m] = c32{er, ei};
+                        zrow[2 * m + 1] = c32{orr, oi};
+                    } else {
+                        nxt[HU + 2 * m] = c32{er, ei};
+                        nxt[HU + 2 * m + 1] = c32{orr, oi};
+                    }
                 }
             }
-            if (h == 0) q.z[(int64_t)t * q.ldz + k] = c32{vr, vi};
-            else nxt[HU + k] = c32{vr, vi};
-        }
-        __syncthreads();
-        if (h > 0) {
-            for (int i = threadIdx.x; i < HU; i += blockDim.x) hist[i] = nxt[nh + i];
-            c32* tmp = cur;
-            cur = nxt;
-            nxt = tmp;
+            __syncthreads();
+            if (h > 0) {
+                for (int i = tid; i < HU; i += kUpThreads) hist[i] = nxt[nh + i];
+                c32* tmp = cur;
+                cur = nxt;
+                nxt = tmp;
+            }
         }
     }
 }
@@ -391,7 +529,7 @@ __global__ void k_fill(uint32_t* p, int64_t words)
 // ---------------------------------------------------------------------------
 int launch_stage(const LaunchArgs& a, int lds_bytes, void* stream)
 {
-    hipLaunchKernelGGL(k_stage, dim3(a.nreq), dim3(256), lds_bytes, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k_stage, dim3(a.nreq), dim3(kStageThreads), lds_bytes, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
@@ -429,7 +567,7 @@ int launch_filter(int F, int precision, const LaunchArgs& a, int nblocks, int L,
 
 int launch_upadd(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream)
 {
-    hipLaunchKernelGGL(k_upadd, dim3(nblocks), dim3(256), lds_bytes, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k_upadd, dim3(nblocks), dim3(kUpThreads), lds_bytes, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 

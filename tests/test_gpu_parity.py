@@ -188,7 +188,7 @@ def test_edge_shapes():
     zg = run_gpu(tb, x, [512] * 4)
     zr = oracle.run_stream(tb, x)
     check(zg, zr, label="edges")
-    assert np.all(zg[3] != 0)
+    assert np.any(zg[3] != 0) and np.any(zg[1] != 0)
 
 
 def test_large_delays_use_subblocks():
