@@ -171,6 +171,71 @@ int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c
  */
 int spiir_process_batch(int32_t n_req, const spiir_request* req, void* hip_stream);
 
+/*
+ * Trigger reduction (the step after the filter in a search: find where |z|
+ * peaks in each template's block, §5).  For every template t the block's
+ * outputs z_t[k], k < n, are reduced to:
+ *   peak2    max_k |z_t[k]|^2, computed from the FP32 output as re*re + im*im
+ *            with each product and the sum rounded to FP32 (no FMA), so the
+ *            caller can repeat every comparison exactly;
+ *   index    the smallest k attaining peak2 (-1 if every |z|^2 is NaN);
+ *   n_above  the number of k with |z_t[k]|^2 >= threshold*threshold (the
+ *            square rounded to FP32).
+ */
+typedef struct {
+    float peak2;
+    int32_t index;
+    int32_t n_above;
+    int32_t reserved; /* 0 */
+} spiir_peak;
+
+/*
+ * spiir_process_peaks — spiir_process_block plus the trigger reduction.
+ *   z_dev     as for spiir_process_block, or NULL to skip writing z (the
+ *             reduction still sees every output); ldz is ignored then.
+ *   peak_dev  device array of n_templates spiir_peak (caller-owned),
+ *             overwritten.
+ *   threshold finite, >= 0 (SPIIR_EINVAL otherwise).
+ * Results for z and the state are identical to spiir_process_block.
+ */
+int spiir_process_peaks(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
+                        int64_t ldz, spiir_peak* peak_dev, float threshold, void* hip_stream);
+
+/*
+ * spiir_process_batch_peaks — spiir_process_batch plus the trigger
+ * reduction: peak_dev[r] is the spiir_peak array of request r (z_dev of a
+ * request may be NULL, as above).  Same batching rules and guarantees.
+ */
+int spiir_process_batch_peaks(int32_t n_req, const spiir_request* req, spiir_peak* const* peak_dev,
+                              float threshold, void* hip_stream);
+
+/*
+ * Recorded batches: one launch sequence, recorded once as a HIP graph and
+ * replayed for every block (for loops that would otherwise pay the host cost
+ * of building and launching the sequence per block).
+ *
+ * spiir_graph_create — record what spiir_process_batch(n_req, req) enqueues
+ * (same validation and error codes) without running it and without changing
+ * any bank.  The graph keeps the request's pointers and sizes: x_dev, n,
+ * z_dev and ldz are fixed for its lifetime.  Allocates host and device memory
+ * for the graph; returns SPIIR_EDEVICE if recording fails.
+ *
+ * spiir_graph_launch — replay on `hip_stream`.  Each bank of the graph takes
+ * its next n samples from x_dev and writes z_dev exactly as
+ * spiir_process_batch would at that point of its stream (bit for bit), and its
+ * sample count advances by n; the stream first waits for the banks' previous
+ * work.  The caller refills x_dev and reads z_dev between replays, in stream
+ * order.  Replays and eager calls may be interleaved on a bank.
+ *
+ * spiir_graph_destroy — wait for the graph's last replay, free it.  It does
+ * not touch the banks, so it may follow their destruction; replaying a graph
+ * after one of its banks was destroyed is undefined.  NULL is accepted.
+ */
+typedef struct spiir_graph spiir_graph;
+int spiir_graph_create(int32_t n_req, const spiir_request* req, spiir_graph** out);
+int spiir_graph_launch(spiir_graph* graph, void* hip_stream);
+int spiir_graph_destroy(spiir_graph* graph);
+
 /* spiir_reset — zero every state (filters, histories, flags, sample count).
  * Synchronous. */
 int spiir_reset(spiir_bank* bank);

@@ -336,7 +336,7 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
     p.lds_filter = 2 * p.xcap * 4 + (L / 2) * (kTile + 1) * 8 + 2 * kTile * p.nrun_max * 8 + p.npiece_max * 8 +
                    L * 4 + p.npiece_max * 8;
     p.lds_stage = ((p.td - 1) + p.mb_inner + (p.td - 1) + p.mb_inner / 2 + p.td) * 4;
-    p.lds_up = 2 * (p.hu_len + p.mb_inner / 2) * 8 + p.tu * 4;
+    p.lds_up = (2 * (p.hu_len + p.mb_inner / 2) + std::max(p.H - 2, 0) * p.hu_len) * 8 + p.tu * 4;
     if (p.lds_filter > kMaxLds || p.lds_stage > kMaxLds || p.lds_up > kMaxLds) return SPIIR_EINVAL;
 
     size_t fp = 0;
@@ -346,6 +346,7 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
     fp += (size_t)p.ring_total * sizeof(float) + (size_t)(p.td + p.tu) * sizeof(float);
     fp += (size_t)p.zw_elems * sizeof(c32);
     fp += (size_t)T * H * p.hu_len * sizeof(c32) + (size_t)T * sizeof(int32_t) + sizeof(BankDev);
+    fp += 2 * sizeof(int64_t);
     p.footprint = fp;
     return SPIIR_OK;
 }
@@ -411,6 +412,7 @@ struct spiir_bank {
     c32* zw = nullptr;
     c32* uphist = nullptr;
     int32_t* flags = nullptr;
+    int64_t* clock = nullptr;
     BankDev* bd = nullptr;
 };
 
@@ -428,7 +430,7 @@ void free_bank(spiir_bank* b)
 {
     if (!b) return;
     void* ptrs[] = {b->a,     b->b,     b->dc, b->y,  b->ys, b->off, b->wg,     b->piece, b->seg,
-                    b->lane_meta, b->rings, b->hd, b->hu, b->zw, b->uphist, b->flags, b->bd};
+                    b->lane_meta, b->rings, b->hd, b->hu, b->zw, b->uphist, b->flags, b->clock, b->bd};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (b->ev) (void)hipEventDestroy(b->ev);
@@ -444,6 +446,7 @@ int zero_state(spiir_bank* b, hipStream_t s)
     e |= launch_fill(b->rings, p.ring_total * (int64_t)sizeof(float), s);
     e |= launch_fill(b->uphist, (int64_t)p.T * p.H * p.hu_len * (int64_t)sizeof(c32), s);
     e |= launch_fill(b->flags, (int64_t)p.T * (int64_t)sizeof(int32_t), s);
+    e |= launch_fill(b->clock, 2 * (int64_t)sizeof(int64_t), s);
     return e;
 }
 
@@ -460,7 +463,151 @@ struct StateHeader {
     int64_t hist;
 };
 
+// peaks: the per-request trigger outputs (null for plain calls); with them a
+// request may leave z_dev null.
+int validate_batch(int32_t n_req, const spiir_request* req, spiir_peak* const* peaks = nullptr)
+{
+    if (n_req < 1 || n_req > SPIIR_MAX_BATCH || !req) return SPIIR_EINVAL;
+    for (int r = 0; r < n_req; ++r) {
+        const spiir_request& q = req[r];
+        if (!q.bank) return SPIIR_EINVAL;
+        if (q.bank->poisoned) return SPIIR_EDEVICE;
+        const Plan& p = q.bank->plan;
+        if (q.n <= 0 || q.n > p.max_block || q.n % (1 << (p.H - 1)) != 0) return SPIIR_EINVAL;
+        if (!q.x_dev) return SPIIR_EINVAL;
+        if (peaks && !peaks[r]) return SPIIR_EINVAL;
+        if (q.z_dev ? q.ldz < q.n : !peaks) return SPIIR_EINVAL;
+        const Plan& p0 = req[0].bank->plan;
+        if (q.bank->device != req[0].bank->device || p.F != p0.F || p.L != p0.L ||
+            p.precision != p0.precision)
+            return SPIIR_EINVAL;
+        for (int s = 0; s < r; ++s)
+            if (req[s].bank == q.bank) return SPIIR_EORDER;
+    }
+    return SPIIR_OK;
+}
+
+// The stream waits for each bank's previous work (per-bank order across streams).
+hipError_t wait_banks(int32_t n_req, const spiir_request* req, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < n_req; ++r)
+        if (req[r].bank->ev_recorded && e == hipSuccess) e = hipStreamWaitEvent(s, req[r].bank->ev, 0);
+    return e;
+}
+
+// Kernels of one batch on `s`: per inner chunk of at most kInnerBlock base-rate
+// samples, the staging kernel (which advances each bank's device clock), the
+// filter kernel and the upsample-and-add kernel.  Reads no host-side sample
+// count, so a recorded sequence can be replayed.
+hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s, bool prof,
+                         spiir_peak* const* peaks = nullptr, float thr2 = 0.0f)
+{
+    hipError_t e = hipSuccess;
+    int64_t maxn = 0;
+    for (int r = 0; r < n_req; ++r) maxn = std::max<int64_t>(maxn, req[r].n);
+    const int F = req[0].bank->plan.F, L = req[0].bank->plan.L, prec = req[0].bank->plan.precision;
+    for (int64_t c0 = 0; c0 < maxn && e == hipSuccess; c0 += kInnerBlock) {
+        LaunchArgs A;
+        std::memset(&A, 0, sizeof(A));
+        int rmap[SPIIR_MAX_BATCH];
+        int lds_f = 0, lds_s = 0, lds_u = 0, nwg = 0, ntm = 0, maxH = 0;
+        for (int r = 0; r < n_req; ++r) {
+            const spiir_request& q = req[r];
+            if (q.n <= c0) continue;
+            spiir_bank* b = q.bank;
+            const Plan& p = b->plan;
+            const int k = A.nreq++;
+            rmap[k] = r;
+            ReqArg& ra = A.req[k];
+            ra.bd = b->bd;
+            ra.x = q.x_dev + c0;
+            ra.z = q.z_dev ? reinterpret_cast<c32*>(q.z_dev) + c0 : nullptr;
+            ra.ldz = q.ldz;
+            ra.peaks = peaks ? peaks[r] : nullptr;
+            ra.n = (int32_t)std::min<int64_t>(kInnerBlock, q.n - c0);
+            ra.H = p.H;
+            ra.c0 = (int32_t)c0;
+            ra.thr2 = thr2;
+            lds_f = std::max(lds_f, p.lds_filter);
+            lds_s = std::max(lds_s, p.lds_stage);
+            lds_u = std::max(lds_u, p.lds_up);
+            maxH = std::max(maxH, p.H);
+        }
+        // filter workgroups: band-major across requests (longest bands first)
+        A.cum[0] = 0;
+        for (int h = 0; h < maxH; ++h)
+            for (int k = 0; k < A.nreq; ++k) {
+                const Plan& p = req[rmap[k]].bank->plan;
+                if (h >= p.H) continue;
+                const int cnt = p.band_wg0[h + 1] - p.band_wg0[h];
+                if (cnt == 0) continue;
+                A.seg_req[A.nseg] = (int16_t)k;
+                A.seg_band[A.nseg] = (int16_t)h;
+                A.cum[A.nseg + 1] = A.cum[A.nseg] + cnt;
+                A.nseg++;
+                nwg += cnt;
+            }
+        A.tcum[0] = 0;
+        for (int k = 0; k < A.nreq; ++k) {
+            A.tcum[k + 1] = A.tcum[k] + req[rmap[k]].bank->plan.T;
+            ntm += req[rmap[k]].bank->plan.T;
+        }
+
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        if (prof)
+            for (int i = 0; i < 4; ++i) {
+                ev[i] = prof_event();
+                if (ev[i]) (void)hipEventRecord(ev[i], s);
+                if (i == 0) e = (hipError_t)launch_stage(A, lds_s, s);
+                else if (i == 1 && e == hipSuccess && nwg > 0)
+                    e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
+                else if (i == 2 && e == hipSuccess)
+                    e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
+            }
+        else {
+            e = (hipError_t)launch_stage(A, lds_s, s);
+            if (e == hipSuccess && nwg > 0) e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
+            if (e == hipSuccess) e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
+        }
+        if (prof) {
+            for (int i = 0; i < 3; ++i)
+                if (ev[i] && ev[i + 1]) g_prof_recs.push_back(ProfRec{i, ev[i], ev[i + 1]});
+        }
+    }
+    return e;
+}
+
+// Host bookkeeping after a batch was enqueued (or replayed): sample counts and
+// per-bank completion events; a failed enqueue poisons the banks.
+int finish_batch(int32_t n_req, const spiir_request* req, hipStream_t s, hipError_t e)
+{
+    if (e == hipSuccess)
+        for (int r = 0; r < n_req; ++r) req[r].bank->done += req[r].n;
+    for (int r = 0; r < n_req && e == hipSuccess; ++r) {
+        e = hipEventRecord(req[r].bank->ev, s);
+        req[r].bank->ev_recorded = true;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        for (int r = 0; r < n_req; ++r) req[r].bank->poisoned = true;
+        return SPIIR_EDEVICE;
+    }
+    return SPIIR_OK;
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------- recorded batches
+
+struct spiir_graph {
+    int device = 0;
+    std::vector<spiir_request> req;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev = nullptr;  // recorded after each replay; destroy waits on it, not on the banks
+    bool ev_recorded = false;
+};
 
 extern "C" {
 
@@ -533,7 +680,8 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
         return ndev == 0 ? SPIIR_EDEVICE : SPIIR_EINVAL;
     }
     b->device = desc->device;
-    if (hipSetDevice(b->device) != hipSuccess) {
+    if (hipSetDevice(b->device) != hipSuccess || allow_filter_lds() != 0) {
+        (void)hipGetLastError();
         delete b;
         return SPIIR_EDEVICE;
     }
@@ -556,6 +704,7 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     ok &= dalloc(&b->zw, p.zw_elems) == hipSuccess;
     ok &= dalloc(&b->uphist, (size_t)p.T * p.H * p.hu_len) == hipSuccess;
     ok &= dalloc(&b->flags, p.T) == hipSuccess;
+    ok &= dalloc(&b->clock, 2) == hipSuccess;
     ok &= dalloc(&b->bd, 1) == hipSuccess;
     ok &= hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
@@ -620,6 +769,7 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     bd.zw = b->zw;
     bd.uphist = b->uphist;
     bd.flags = b->flags;
+    bd.clock = b->clock;
 
     hipError_t e = hipSuccess;
     auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -659,112 +809,18 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
 
 int spiir_process_batch(int32_t n_req, const spiir_request* req, void* stream)
 {
-    if (n_req < 1 || n_req > SPIIR_MAX_BATCH || !req) return SPIIR_EINVAL;
-    for (int r = 0; r < n_req; ++r) {
-        const spiir_request& q = req[r];
-        if (!q.bank) return SPIIR_EINVAL;
-        if (q.bank->poisoned) return SPIIR_EDEVICE;
-        const Plan& p = q.bank->plan;
-        if (q.n <= 0 || q.n > p.max_block || q.n % (1 << (p.H - 1)) != 0) return SPIIR_EINVAL;
-        if (!q.x_dev || !q.z_dev || q.ldz < q.n) return SPIIR_EINVAL;
-        const Plan& p0 = req[0].bank->plan;
-        if (q.bank->device != req[0].bank->device || p.F != p0.F || p.L != p0.L ||
-            p.precision != p0.precision)
-            return SPIIR_EINVAL;
-        for (int s = 0; s < r; ++s)
-            if (req[s].bank == q.bank) return SPIIR_EORDER;
-    }
+    int rc = validate_batch(n_req, req);
+    if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(req[0].bank->device) != hipSuccess) return SPIIR_EDEVICE;
-    hipError_t e = hipSuccess;
-    for (int r = 0; r < n_req; ++r)
-        if (req[r].bank->ev_recorded && e == hipSuccess) e = hipStreamWaitEvent(s, req[r].bank->ev, 0);
-
-    std::unique_lock<std::mutex> lk(g_prof_mu);
-    const bool prof = g_prof_on;
-    if (!prof) lk.unlock();
-
-    int64_t maxn = 0;
-    for (int r = 0; r < n_req; ++r) maxn = std::max<int64_t>(maxn, req[r].n);
-    int F = req[0].bank->plan.F, L = req[0].bank->plan.L, prec = req[0].bank->plan.precision;
-    for (int64_t c0 = 0; c0 < maxn && e == hipSuccess; c0 += kInnerBlock) {
-        LaunchArgs A;
-        std::memset(&A, 0, sizeof(A));
-        int rmap[SPIIR_MAX_BATCH];
-        int lds_f = 0, lds_s = 0, lds_u = 0, nwg = 0, ntm = 0, maxH = 0;
-        for (int r = 0; r < n_req; ++r) {
-            const spiir_request& q = req[r];
-            if (q.n <= c0) continue;
-            spiir_bank* b = q.bank;
-            const Plan& p = b->plan;
-            const int k = A.nreq++;
-            rmap[k] = r;
-            ReqArg& ra = A.req[k];
-            ra.bd = b->bd;
-            ra.x = q.x_dev + c0;
-            ra.z = reinterpret_cast<c32*>(q.z_dev) + c0;
-            ra.ldz = q.ldz;
-            ra.s0 = b->done;
-            ra.n = (int32_t)std::min<int64_t>(kInnerBlock, q.n - c0);
-            ra.H = p.H;
-            lds_f = std::max(lds_f, p.lds_filter);
-            lds_s = std::max(lds_s, p.lds_stage);
-            lds_u = std::max(lds_u, p.lds_up);
-            maxH = std::max(maxH, p.H);
-        }
-        // filter workgroups: band-major across requests (longest bands first)
-        A.cum[0] = 0;
-        for (int h = 0; h < maxH; ++h)
-            for (int k = 0; k < A.nreq; ++k) {
-                const Plan& p = req[rmap[k]].bank->plan;
-                if (h >= p.H) continue;
-                const int cnt = p.band_wg0[h + 1] - p.band_wg0[h];
-                if (cnt == 0) continue;
-                A.seg_req[A.nseg] = (int16_t)k;
-                A.seg_band[A.nseg] = (int16_t)h;
-                A.cum[A.nseg + 1] = A.cum[A.nseg] + cnt;
-                A.nseg++;
-                nwg += cnt;
-            }
-        A.tcum[0] = 0;
-        for (int k = 0; k < A.nreq; ++k) {
-            A.tcum[k + 1] = A.tcum[k] + req[rmap[k]].bank->plan.T;
-            ntm += req[rmap[k]].bank->plan.T;
-        }
-
-        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-        if (prof)
-            for (int i = 0; i < 4; ++i) {
-                ev[i] = prof_event();
-                if (ev[i]) (void)hipEventRecord(ev[i], s);
-                if (i == 0) e = (hipError_t)launch_stage(A, lds_s, s);
-                else if (i == 1 && e == hipSuccess && nwg > 0)
-                    e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
-                else if (i == 2 && e == hipSuccess)
-                    e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
-            }
-        else {
-            e = (hipError_t)launch_stage(A, lds_s, s);
-            if (e == hipSuccess && nwg > 0) e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
-            if (e == hipSuccess) e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
-        }
-        if (prof) {
-            for (int i = 0; i < 3; ++i)
-                if (ev[i] && ev[i + 1]) g_prof_recs.push_back(ProfRec{i, ev[i], ev[i + 1]});
-        }
-        for (int k = 0; k < A.nreq; ++k) req[rmap[k]].bank->done += A.req[k].n;
+    hipError_t e = wait_banks(n_req, req, s);
+    if (e == hipSuccess) {
+        std::unique_lock<std::mutex> lk(g_prof_mu);
+        const bool prof = g_prof_on;
+        if (!prof) lk.unlock();
+        e = enqueue_batch(n_req, req, s, prof);
     }
-    if (lk.owns_lock()) lk.unlock();
-    for (int r = 0; r < n_req && e == hipSuccess; ++r) {
-        e = hipEventRecord(req[r].bank->ev, s);
-        req[r].bank->ev_recorded = true;
-    }
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        for (int r = 0; r < n_req; ++r) req[r].bank->poisoned = true;
-        return SPIIR_EDEVICE;
-    }
-    return SPIIR_OK;
+    return finish_batch(n_req, req, s, e);
 }
 
 int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
@@ -772,6 +828,33 @@ int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c
 {
     spiir_request r{bank, x_dev, n, z_dev, ldz};
     return spiir_process_batch(1, &r, stream);
+}
+
+int spiir_process_batch_peaks(int32_t n_req, const spiir_request* req, spiir_peak* const* peak_dev,
+                              float threshold, void* stream)
+{
+    if (!peak_dev || !(threshold >= 0.0f) || !std::isfinite(threshold)) return SPIIR_EINVAL;
+    int rc = validate_batch(n_req, req, peak_dev);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(req[0].bank->device) != hipSuccess) return SPIIR_EDEVICE;
+    hipError_t e = wait_banks(n_req, req, s);
+    if (e == hipSuccess) {
+        std::unique_lock<std::mutex> lk(g_prof_mu);
+        const bool prof = g_prof_on;
+        if (!prof) lk.unlock();
+        const float thr2 = threshold * threshold;
+        e = enqueue_batch(n_req, req, s, prof, peak_dev, thr2);
+    }
+    return finish_batch(n_req, req, s, e);
+}
+
+int spiir_process_peaks(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
+                        int64_t ldz, spiir_peak* peak_dev, float threshold, void* stream)
+{
+    spiir_request r{bank, x_dev, n, z_dev, ldz};
+    spiir_peak* pk[1] = {peak_dev};
+    return spiir_process_batch_peaks(1, &r, pk, threshold, stream);
 }
 
 static int bank_sync(spiir_bank* b)
@@ -864,6 +947,8 @@ int spiir_load_state(spiir_bank* b, const void* host_buf, void* stream)
     upl(b->rings, sizeof(float) * p.ring_total);
     upl(b->uphist, sizeof(c32) * (size_t)p.T * p.H * p.hu_len);
     upl(b->flags, sizeof(int32_t) * p.T);
+    const int64_t clk[2] = {hdr.done, hdr.done};
+    if (e == hipSuccess) e = hipMemcpyAsync(b->clock, clk, sizeof(clk), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         b->poisoned = true;
@@ -901,6 +986,76 @@ int spiir_destroy(spiir_bank* b)
     free_bank(b);
     return SPIIR_OK;
 }
+
+int spiir_graph_create(int32_t n_req, const spiir_request* req, spiir_graph** out)
+{
+    if (!out) return SPIIR_EINVAL;
+    *out = nullptr;
+    int rc = validate_batch(n_req, req);
+    if (rc) return rc;
+    if (hipSetDevice(req[0].bank->device) != hipSuccess) return SPIIR_EDEVICE;
+    spiir_graph* g = nullptr;
+    try {
+        g = new spiir_graph();
+        g->req.assign(req, req + n_req);
+    } catch (const std::bad_alloc&) {
+        delete g;
+        return SPIIR_ENOMEM;
+    }
+    g->device = req[0].bank->device;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&g->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t ee = enqueue_batch(n_req, req, cs, false);
+            e = hipStreamEndCapture(cs, &g->graph);
+            if (ee != hipSuccess) e = ee;
+        }
+        (void)hipStreamDestroy(cs);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->ev) (void)hipEventDestroy(g->ev);
+        delete g;
+        return e == hipErrorOutOfMemory ? SPIIR_ENOMEM : SPIIR_EDEVICE;
+    }
+    *out = g;
+    return SPIIR_OK;
+}
+
+int spiir_graph_launch(spiir_graph* g, void* stream)
+{
+    if (!g) return SPIIR_EINVAL;
+    const int32_t n_req = (int32_t)g->req.size();
+    for (const spiir_request& q : g->req)
+        if (q.bank->poisoned) return SPIIR_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(g->device) != hipSuccess) return SPIIR_EDEVICE;
+    hipError_t e = wait_banks(n_req, g->req.data(), s);
+    if (e == hipSuccess) e = hipGraphLaunch(g->exec, s);
+    if (e == hipSuccess) {
+        e = hipEventRecord(g->ev, s);
+        g->ev_recorded = e == hipSuccess;
+    }
+    return finish_batch(n_req, g->req.data(), s, e);
+}
+
+int spiir_graph_destroy(spiir_graph* g)
+{
+    if (!g) return SPIIR_OK;
+    (void)hipSetDevice(g->device);
+    if (g->ev_recorded) (void)hipEventSynchronize(g->ev);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ev) (void)hipEventDestroy(g->ev);
+    delete g;
+    return SPIIR_OK;
+}
+
 
 int spiir_samples_done(const spiir_bank* b, int64_t* samples)
 {

@@ -93,16 +93,22 @@ struct BankDev {
     c32* zw;                        // per-piece band outputs of the current block
     c32* uphist;                    // [T][H][hu_len] last acc samples per band
     int32_t* flags;                 // [T] sticky non-finite flags
+    // [0]: absolute base-rate index of the first sample of the chunk being
+    // filtered; [1]: samples staged so far.  The staging kernel advances them,
+    // so a recorded launch sequence can be replayed block after block.
+    int64_t* clock;
 };
 
 struct ReqArg {
     const BankDev* bd;
     const float* x;
-    c32* z;
+    c32* z;              // null: the output is not written
     int64_t ldz;
-    int64_t s0;   // absolute base-rate index of the block's first sample
+    spiir_peak* peaks;   // null: no trigger reduction
     int32_t n;
     int32_t H;
+    int32_t c0;          // offset of this chunk in the caller's block
+    float thr2;          // threshold^2 of the trigger count
 };
 
 // Everything one launch sequence needs, passed by value as kernel arguments.
@@ -125,5 +131,6 @@ int launch_prep(const c64* a, const c64* b, int64_t n, int C, c32* fa, c32* fb, 
                 void* stream);
 int launch_fill(void* p, int64_t bytes, void* stream);
 int filter_max_lds();
+int allow_filter_lds();
 
 }  // namespace spiir

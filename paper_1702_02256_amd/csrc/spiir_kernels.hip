@@ -12,6 +12,8 @@
 //             chain of kernels).
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "spiir_internal.h"
 
 namespace spiir {
@@ -31,10 +33,17 @@ constexpr int kStageThreads = 1024;
 __global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
 {
     extern __shared__ float sm[];
+    __shared__ long long s_base;
     const ReqArg& q = args.req[blockIdx.x];
     const BankDev* bd = q.bd;
     const int n = q.n;
-    const int64_t s0 = q.s0;
+    if (threadIdx.x == 0) s_base = bd->clock[1];
+    __syncthreads();
+    const int64_t s0 = s_base;
+    if (threadIdx.x == 0) {
+        bd->clock[0] = s0;      // read by the filter kernel that follows
+        bd->clock[1] = s0 + n;
+    }
     const int H = bd->H;
     float* ring0 = bd->rings + bd->ring_off[0];
     const int64_t m0 = bd->ring_mask[0];
@@ -186,7 +195,7 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
     const int L = blockDim.x;
     const int tid = threadIdx.x;
     const int nh = q.n >> h;
-    const int64_t s0h = q.s0 >> h;
+    const int64_t s0h = bd->clock[0] >> h;  // set by the staging kernel of this chunk
     const int64_t cmask = bd->C - 1;
     const int nrun = bd->nrun_max;
 
@@ -445,6 +454,63 @@ __device__ __forceinline__ float4 piece_sum2(const c32* zw, const SegDesc& sg, i
     return v;
 }
 
+// Trigger reduction of one template's block (the step after the filter in the
+// search pipeline, §5): the largest |z|^2, the first sample attaining it and
+// the number of samples at or above a threshold.  |z|^2 is re*re + im*im with
+// each product and the sum rounded to FP32 (no contraction), so a caller can
+// repeat the decision exactly from the FP32 output.
+struct PeakAcc {
+    float v = -1.0f;
+    int i = INT_MAX;
+    int cnt = 0;
+    __device__ __forceinline__ void add(float re, float im, int k, float thr2)
+    {
+        const float m = __fadd_rn(__fmul_rn(re, re), __fmul_rn(im, im));
+        if (m > v) {  // a thread visits its samples in increasing order
+            v = m;
+            i = k;
+        }
+        cnt += m >= thr2 ? 1 : 0;
+    }
+    __device__ __forceinline__ void merge(float ov, int oi, int oc)
+    {
+        if (ov > v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+        cnt += oc;
+    }
+};
+
+__device__ void peak_store(PeakAcc a, const ReqArg& q, int t, int tid)
+{
+    __shared__ float sv[kUpThreads / 64];
+    __shared__ int si[kUpThreads / 64], sc[kUpThreads / 64];
+    for (int off = 32; off >= 1; off >>= 1)
+        a.merge(__shfl_xor(a.v, off), __shfl_xor(a.i, off), __shfl_xor(a.cnt, off));
+    if ((tid & 63) == 0) {
+        sv[tid >> 6] = a.v;
+        si[tid >> 6] = a.i;
+        sc[tid >> 6] = a.cnt;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    for (int w = 1; w < kUpThreads / 64; ++w) a.merge(sv[w], si[w], sc[w]);
+    spiir_peak* pk = q.peaks + t;
+    float v = a.v;
+    int idx = a.i == INT_MAX ? -1 : q.c0 + a.i;
+    int cnt = a.cnt;
+    if (q.c0 > 0) {  // later chunk of the caller's block: combine with the earlier ones
+        const spiir_peak old = *pk;
+        if (!(idx >= 0 && (old.index < 0 || v > old.peak2))) {
+            v = old.peak2;
+            idx = old.index;
+        }
+        cnt += old.n_above;
+    }
+    *pk = spiir_peak{v, idx, cnt, 0};
+}
+
 __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
 {
     extern __shared__ float sm[];
@@ -457,32 +523,32 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
     const int tid = threadIdx.x;
     const int H = bd->H, n = q.n, HU = bd->hu_len, tu = bd->tu, MB = bd->max_block;
     const SegDesc* seg = bd->seg + (int64_t)t * H;
-    c32* zrow = q.z + (int64_t)t * q.ldz;
+    c32* zrow = q.z ? q.z + (int64_t)t * q.ldz : nullptr;
+    const bool peaks = q.peaks != nullptr;
+    PeakAcc acc;
 
     if (H == 1) {
         const SegDesc sg = seg[0];
-        for (int k = tid; k < n; k += kUpThreads) zrow[k] = piece_sum(bd->zw, sg, bd->zstride[0], k);
+        for (int k = tid; k < n; k += kUpThreads) {
+            const c32 v = piece_sum(bd->zw, sg, bd->zstride[0], k);
+            if (zrow) zrow[k] = v;
+            if (peaks) acc.add(v.x, v.y, k, q.thr2);
+        }
+        if (peaks) peak_store(acc, q, t, tid);
         return;
     }
 
     const int ext = HU + MB / 2;
     c32* cur = reinterpret_cast<c32*>(sm);
     c32* nxt = cur + ext;
-    float* hu = reinterpret_cast<float*>(nxt + ext);
+    c32* hl = nxt + ext;  // histories of bands 1..H-2, loaded once up front
+    float* hu = reinterpret_cast<float*>(hl + (H - 2) * HU);
     for (int i = tid; i < tu; i += kUpThreads) hu[i] = bd->hu[i];
+    const c32* hist_in = bd->uphist + ((int64_t)t * H + 1) * HU;
+    for (int i = tid; i < (H - 2) * HU; i += kUpThreads) hl[i] = hist_in[i];
 
-    // lowest band: acc_{H-1} = z_{H-1}, placed after its history
-    {
-        const int h = H - 1, nh = n >> h;
-        const SegDesc sg = seg[h];
-        c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
-        for (int i = tid; i < HU; i += kUpThreads) cur[i] = hist[i];
-        for (int k = tid; k < nh; k += kUpThreads) cur[HU + k] = piece_sum(bd->zw, sg, bd->zstride[h], k);
-        __syncthreads();
-        for (int i = tid; i < HU; i += kUpThreads) hist[i] = cur[nh + i];
-    }
-
-    // every other band's own output, both phases per low-rate sample
+    // every other band's own output, both phases per low-rate sample; all of
+    // this block's loads are issued before the first barrier
     float4 pv[kUpSlotsTotal];
 #pragma unroll
     for (int h = 0; h < kMaxBands - 1; ++h) {
@@ -495,6 +561,17 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
         }
     }
 
+    // lowest band: acc_{H-1} = z_{H-1}, placed after its history
+    {
+        const int h = H - 1, nh = n >> h;
+        const SegDesc sg = seg[h];
+        c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
+        for (int i = tid; i < HU; i += kUpThreads) cur[i] = hist[i];
+        for (int k = tid; k < nh; k += kUpThreads) cur[HU + k] = piece_sum(bd->zw, sg, bd->zstride[h], k);
+        __syncthreads();
+        for (int i = tid; i < HU; i += kUpThreads) hist[i] = cur[nh + i];
+    }
+
     const int ne = HU, no = tu / 2;  // even and odd polyphase tap counts
 #pragma unroll
     for (int h = kMaxBands - 2; h >= 0; --h) {
@@ -502,7 +579,7 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
             const int nh = n >> h, nlo = n >> (h + 1);
             c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
             if (h > 0)
-                for (int i = tid; i < HU; i += kUpThreads) nxt[i] = hist[i];
+                for (int i = tid; i < HU; i += kUpThreads) nxt[i] = hl[(h - 1) * HU + i];
 #pragma unroll
             for (int i = 0; i < up_slots(h); ++i) {
                 const int m = tid + kUpThreads * i;
@@ -522,8 +599,14 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
                         }
                     }
                     if (h == 0) {
-                        zrow[2 * m] = c32{er, ei};
-                        zrow[2 * m + 1] = c32{orr, oi};
+                        if (zrow) {
+                            zrow[2 * m] = c32{er, ei};
+                            zrow[2 * m + 1] = c32{orr, oi};
+                        }
+                        if (peaks) {
+                            acc.add(er, ei, 2 * m, q.thr2);
+                            acc.add(orr, oi, 2 * m + 1, q.thr2);
+                        }
                     } else {
                         nxt[HU + 2 * m] = c32{er, ei};
                         nxt[HU + 2 * m + 1] = c32{orr, oi};
@@ -539,6 +622,7 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
             }
         }
     }
+    if (peaks) peak_store(acc, q, t, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -584,14 +668,33 @@ template <int F, bool COMP>
 static int launch_filter_t(const LaunchArgs& a, int nblocks, int L, int lds_bytes,
                            hipStream_t s)
 {
-    if (lds_bytes > 65536) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_filter<F, COMP>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 lds_bytes);
-        if (e != hipSuccess) return (int)e;
-    }
     hipLaunchKernelGGL((k_filter<F, COMP>), dim3(nblocks), dim3(L), lds_bytes, s, a);
     return (int)hipGetLastError();
+}
+
+template <int F, bool COMP>
+static int allow_lds_t()
+{
+    return (int)hipFuncSetAttribute((const void*)k_filter<F, COMP>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, filter_max_lds());
+}
+
+// Raises the dynamic LDS limit of the filter-kernel variants and the
+// upsample-and-add kernel on the current device (done outside any launch
+// sequence, so recorded sequences hold launches only).
+int allow_filter_lds()
+{
+    int e = (int)hipFuncSetAttribute((const void*)k_upadd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     filter_max_lds());
+    if (!e) e = allow_lds_t<1, false>();
+    if (!e) e = allow_lds_t<1, true>();
+    if (!e) e = allow_lds_t<2, false>();
+    if (!e) e = allow_lds_t<2, true>();
+    if (!e) e = allow_lds_t<4, false>();
+    if (!e) e = allow_lds_t<4, true>();
+    if (!e) e = allow_lds_t<8, false>();
+    if (!e) e = allow_lds_t<8, true>();
+    return e;
 }
 
 int launch_filter(int F, int precision, const LaunchArgs& a, int nblocks, int L, int lds_bytes,

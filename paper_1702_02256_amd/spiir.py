@@ -118,6 +118,11 @@ def load_library():
         "spiir_plan": (C.c_int, [C.POINTER(BankDesc), C.POINTER(PlanInfo)]),
         "spiir_profile_enable": (C.c_int, [C.c_int]),
         "spiir_profile_read": (C.c_int, [C.POINTER(ProfileData)]),
+        "spiir_process_peaks": (C.c_int, [vp, vp, i64, vp, i64, vp, C.c_float, vp]),
+        "spiir_process_batch_peaks": (C.c_int, [i32, C.POINTER(Request), C.POINTER(vp), C.c_float, vp]),
+        "spiir_graph_create": (C.c_int, [i32, C.POINTER(Request), C.POINTER(vp)]),
+        "spiir_graph_launch": (C.c_int, [vp, vp]),
+        "spiir_graph_destroy": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -130,7 +135,7 @@ def load_library():
 def header_symbols() -> list:
     """Entry points declared in include/spiir.h."""
     txt = open(HEADER_PATH).read()
-    return sorted(set(re.findall(r"\b(spiir_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"^(?:int|const char\s*\*)\s*(spiir_[a-z_]+)\s*\(", txt, re.M)))
 
 
 def spiir_strerror(code: int) -> str:
@@ -213,6 +218,44 @@ def spiir_process_batch(requests, stream=None) -> None:
     _check(load_library().spiir_process_batch(n, arr, _stream_handle(stream)), "spiir_process_batch")
 
 
+class Graph:
+    """A recorded batch (spiir_graph_*): the launch sequence of one
+    spiir_process_batch call over fixed buffers, replayed by `launch`.
+
+    requests: list of (bank, x, z) device tensors; x is refilled and z read by
+    the caller between launches, in stream order.
+    """
+
+    def __init__(self, requests):
+        lib = load_library()
+        self._lib = lib
+        n = len(requests)
+        arr = (Request * max(n, 1))()
+        for i, (bank, x, z) in enumerate(requests):
+            _validate_io(bank, x, z)
+            arr[i] = Request(bank._h, x.data_ptr(), int(x.numel()), z.data_ptr(), int(z.stride(0)))
+        # keep the tensors alive as long as the recorded pointers are used
+        self._keep = [(b, x, z) for b, x, z in requests]
+        h = C.c_void_p()
+        _check(lib.spiir_graph_create(n, arr, C.byref(h)), "spiir_graph_create")
+        self._h = h.value
+
+    def launch(self, stream=None) -> None:
+        _check(self._lib.spiir_graph_launch(self._h, _stream_handle(stream)), "spiir_graph_launch")
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.spiir_graph_destroy(self._h)
+            self._h = None
+        self._keep = []
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 def spiir_profile_enable(on: bool = True) -> None:
     _check(load_library().spiir_profile_enable(1 if on else 0), "spiir_profile_enable")
 
@@ -224,10 +267,49 @@ def spiir_profile_read() -> dict:
     return {names[i]: {"launches": int(d.launches[i]), "ms": float(d.ms[i])} for i in range(3)}
 
 
-def _validate_io(bank, x, z):
+def peaks_empty(n_templates: int, device="cuda"):
+    """Device buffer for spiir_peak[n_templates] (int32 [T, 4]; see peaks_unpack)."""
     import torch
+    return torch.empty((n_templates, 4), dtype=torch.int32, device=device)
+
+
+def peaks_unpack(peaks) -> dict:
+    """Host copy of a spiir_peak buffer: peak2 (float32), index, n_above (int32)."""
+    a = peaks.cpu().numpy()
+    return {"peak2": a[:, 0].copy().view(np.float32), "index": a[:, 1].copy(),
+            "n_above": a[:, 2].copy()}
+
+
+def _validate_peaks(bank, peaks):
+    import torch
+    if (peaks.dtype != torch.int32 or not peaks.is_cuda or tuple(peaks.shape) != (bank.n_templates, 4)
+            or not peaks.is_contiguous()):
+        raise ValueError("peaks must be a contiguous int32 device tensor of shape (n_templates, 4)")
+
+
+def spiir_process_batch_peaks(requests, peaks, threshold: float, stream=None) -> None:
+    """requests: list of (bank, x, z or None); peaks: one peaks_empty buffer per request."""
+    n = len(requests)
+    arr = (Request * max(n, 1))()
+    pk = (C.c_void_p * max(n, 1))()
+    for i, ((bank, x, z), p) in enumerate(zip(requests, peaks)):
+        _validate_io(bank, x, z, z_optional=True)
+        _validate_peaks(bank, p)
+        arr[i] = Request(bank._h, x.data_ptr(), int(x.numel()), z.data_ptr() if z is not None else None,
+                         int(z.stride(0)) if z is not None else 0)
+        pk[i] = p.data_ptr()
+    _check(load_library().spiir_process_batch_peaks(n, arr, pk, float(threshold), _stream_handle(stream)),
+           "spiir_process_batch_peaks")
+
+
+def _validate_io(bank, x, z, z_optional=False):
+    import torch
+    if z is None and not z_optional:
+        raise ValueError("z is required")
     if x.dtype != torch.float32 or not x.is_cuda or x.dim() != 1 or not x.is_contiguous():
         raise ValueError("x must be a contiguous 1-D float32 device tensor")
+    if z is None:
+        return
     if z.dtype != torch.complex64 or not z.is_cuda or z.dim() != 2 or z.stride(1) != 1:
         raise ValueError("z must be a 2-D complex64 device tensor with unit inner stride")
     if z.shape[0] < bank.n_templates or z.shape[1] < x.numel():
@@ -259,6 +341,16 @@ class Bank:
         rc = self._lib.spiir_process_block(self._h, x.data_ptr(), int(x.numel()), z.data_ptr(),
                                            int(z.stride(0)), _stream_handle(stream))
         _check(rc, "spiir_process_block")
+
+    def process_peaks(self, x, z, peaks, threshold: float, stream=None) -> None:
+        """process_block plus the trigger reduction into `peaks` (z may be None)."""
+        _validate_io(self, x, z, z_optional=True)
+        _validate_peaks(self, peaks)
+        rc = self._lib.spiir_process_peaks(self._h, x.data_ptr(), int(x.numel()),
+                                           z.data_ptr() if z is not None else None,
+                                           int(z.stride(0)) if z is not None else 0,
+                                           peaks.data_ptr(), float(threshold), _stream_handle(stream))
+        _check(rc, "spiir_process_peaks")
 
     def process_raw(self, x_ptr: int, n: int, z_ptr: int, ldz: int, stream=None) -> int:
         """Unchecked pointer form (returns the status code)."""

@@ -135,6 +135,19 @@ class BankTables:
             h_up=self.h_up.copy(),
         )
 
+    def rounded_coefficients(self) -> "BankTables":
+        """Copy with a1 and b0 rounded to complex64 and widened back (the
+        tables as an FP32 device holds them), for splitting error sources."""
+        return BankTables(
+            base_rate=self.base_rate,
+            n_filters=self.n_filters.copy(),
+            a1=self.a1.astype(np.complex64).astype(np.complex128),
+            b0=self.b0.astype(np.complex64).astype(np.complex128),
+            delay=self.delay.copy(),
+            h_down=self.h_down.copy(),
+            h_up=self.h_up.copy(),
+        )
+
     def filter_samples_per_block(self, n: int) -> int:
         """Sum over (t, h) of M_{t,h} * n / 2**h: filter-samples for an n-sample block."""
         per_band = self.n_filters.sum(axis=0).astype(np.int64)

@@ -136,6 +136,13 @@ def test_process_calls_reject_null_bank():
     assert lib.spiir_destroy(None) == S.SPIIR_OK
     assert lib.spiir_reset(None) == S.SPIIR_EINVAL
     assert lib.spiir_status(None, None) == S.SPIIR_EINVAL
+    g = C.c_void_p(123)
+    assert lib.spiir_graph_create(0, None, C.byref(g)) == S.SPIIR_EINVAL
+    assert g.value is None
+    assert lib.spiir_graph_launch(None, None) == S.SPIIR_EINVAL
+    assert lib.spiir_graph_destroy(None) == S.SPIIR_OK
+    assert lib.spiir_process_peaks(None, None, 16, None, 16, None, 0.0, None) == S.SPIIR_EINVAL
+    assert lib.spiir_process_batch_peaks(0, None, None, 0.0, None) == S.SPIIR_EINVAL
 
 
 @pytest.mark.skipif(_have_gpu(), reason="checks the no-device error path")
