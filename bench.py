@@ -22,6 +22,37 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
 METRIC = "template-filter-samples/s + real-time templates/GPU; p99 block latency"
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("paper_1702_02256_amd/csrc/spiir_kernels.hip", "paper_1702_02256_amd/csrc/spiir_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summary (profiles/traffic.txt: FETCH_SIZE and WRITE_SIZE runs, each scaled
+    by a plain device copy of known size), or None when no summary exists for
+    it or the kernel sources changed since the counters were taken."""
+    path = os.path.join(HERE, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        f = line.split()
+        # workload kernel sources_sha1 fetch_bytes write_bytes
+        if len(f) == 5 and f[0] == workload and f[1] == kernel and f[2] == src:
+            return {"bytes_per_launch": float(f[3]) + float(f[4]), "read": float(f[3]),
+                    "written": float(f[4])}
+    return None
 
 
 def make_workload(cfg: int, templates: int | None, steps: int):
@@ -250,7 +281,7 @@ def main():
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="seconds of data per stream in the real-time serving run (config 5)")
-    ap.add_argument("--serve-speeds", type=float, nargs="*", default=[10, 30, 60, 90, 120],
+    ap.add_argument("--serve-speeds", type=float, nargs="*", default=[30, 60, 120, 180, 240],
                     help="replay speeds of the capacity sweep (config 5)")
     ap.add_argument("--templates", type=int, default=None)
     ap.add_argument("--filters-per-lane", type=int, default=0)
@@ -428,7 +459,8 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": (lambda t: t and t["bytes_per_launch"])(measured_traffic(wl.name, "k_filter")),
+            "traffic_detail": measured_traffic(wl.name, "k_filter"),
             "algorithmic_flops_per_launch": flops_per_launch,
             "avg_launch_ms": filt_ms,
         },

@@ -81,6 +81,8 @@ struct BankDev {
     const PieceDesc* piece;
     const SegDesc* seg;             // [T*H]
     const int32_t* lane_meta;
+    // Slots of odd lanes hold the swapped form (see one_step): conj(fl32(a1)),
+    // (Im b0, Re b0), conj(carry), and their states are (Im y, Re y).
     const c32* a;                   // per slot: fl32(a1)
     const c32* b;                   // per slot: fl32(b0)
     const c32* dc;                  // per slot: a1^C - fl32(a1)^C (FP64 -> FP32)

@@ -110,9 +110,15 @@ __device__ __forceinline__ void lane_sum(float (&vr)[F], float (&vi)[F])
 // lane sum is combined with the other lane of the pair and stored, one
 // component per lane (the even lane the real part, the odd lane the imaginary
 // part) at pcol[2*j].
+//
+// Odd lanes hold their filters in swapped form, (Im y, Re y), with the tables
+// transformed to match (a1 -> conj(a1), b0 -> (Im b0, Re b0), carry ->
+// conj): the same arithmetic then advances the swapped state.  So every
+// lane's first component sum is what it keeps (even: Re, odd: Im) and its
+// second is what its partner needs, and the pair combine is one DPP add.
 template <int F>
 __device__ __forceinline__ void one_step(const float (&xv)[F], float* __restrict__ pcol, int j,
-                                         bool even_lane, const float (&ar)[F],
+                                         const float (&ar)[F],
                                          const float (&ai)[F], const float (&br)[F],
                                          const float (&bi)[F], float (&yr)[F], float (&yi)[F])
 {
@@ -127,9 +133,7 @@ __device__ __forceinline__ void one_step(const float (&xv)[F], float* __restrict
     }
     lane_sum<F>(tr, ti);
     // even lane: re_even + re_odd; odd lane: im_odd + im_even
-    const float mine = even_lane ? tr[0] : ti[0];
-    const float send = even_lane ? ti[0] : tr[0];
-    pcol[2 * j] = mine + pair_swap(send);
+    pcol[2 * j] = tr[0] + pair_swap(ti[0]);
 }
 
 // A full tile of kTile samples starting at an absolute multiple of kTile.
@@ -139,7 +143,7 @@ __device__ __forceinline__ void one_step(const float (&xv)[F], float* __restrict
 // stores never alias the window, so later loads can be issued ahead of them.
 template <int F>
 __device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* __restrict__ pcol,
-                                          bool even_lane, const float (&ar)[F],
+                                          const float (&ar)[F],
                                           const float (&ai)[F], const float (&br)[F],
                                           const float (&bi)[F], float (&yr)[F], float (&yi)[F])
 {
@@ -155,8 +159,8 @@ __device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* _
             xa[f] = v.x;
             xb[f] = v.y;
         }
-        one_step<F>(xa, pcol, 2 * jj, even_lane, ar, ai, br, bi, yr, yi);
-        one_step<F>(xb, pcol, 2 * jj + 1, even_lane, ar, ai, br, bi, yr, yi);
+        one_step<F>(xa, pcol, 2 * jj, ar, ai, br, bi, yr, yi);
+        one_step<F>(xb, pcol, 2 * jj + 1, ar, ai, br, bi, yr, yi);
     }
 }
 
@@ -164,8 +168,7 @@ __device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* _
 // unshifted window copy.
 template <int F>
 __device__ __forceinline__ void tile_partial(const float* const (&xp)[F], int cnt,
-                                             float* __restrict__ pcol, bool even_lane,
-                                             const float (&ar)[F], const float (&ai)[F],
+                                             float* __restrict__ pcol, const float (&ar)[F], const float (&ai)[F],
                                              const float (&br)[F], const float (&bi)[F],
                                              float (&yr)[F], float (&yi)[F])
 {
@@ -173,7 +176,7 @@ __device__ __forceinline__ void tile_partial(const float* const (&xp)[F], int cn
         float xv[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) xv[f] = xp[f][j];
-        one_step<F>(xv, pcol, j, even_lane, ar, ai, br, bi, yr, yi);
+        one_step<F>(xv, pcol, j, ar, ai, br, bi, yr, yi);
     }
 }
 
@@ -252,7 +255,6 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
     // The pair sum of sample j is entry e = lane/2 of row j: pbuf[e*(kTile+1) + j],
     // the even lane storing its real part and the odd lane its imaginary part.
     const int pe = tid >> 1;
-    const bool even_lane = (tid & 1) == 0;
     float* pcol = reinterpret_cast<float*>(pbuf + pe * (kTile + 1)) + (tid & 1);
     int parity = 0;
 
@@ -283,12 +285,12 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
                     const int par = dl[f] & 1;
                     xp[f] = reinterpret_cast<const float2*>((par ? E1 : E0) + (rel - dl[f] - par));
                 }
-                tile_full<F>(xp, pcol, even_lane, ar, ai, br, bi, yr, yi);
+                tile_full<F>(xp, pcol, ar, ai, br, bi, yr, yi);
             } else {
                 const float* xp[F];
 #pragma unroll
                 for (int f = 0; f < F; ++f) xp[f] = E0 + (rel - dl[f]);
-                tile_partial<F>(xp, cnt, pcol, even_lane, ar, ai, br, bi, yr, yi);
+                tile_partial<F>(xp, cnt, pcol, ar, ai, br, bi, yr, yi);
             }
 
             // carry correction after the last sample of an absolute chunk of C samples
@@ -465,7 +467,8 @@ struct PeakAcc {
     int cnt = 0;
     __device__ __forceinline__ void add(float re, float im, int k, float thr2)
     {
-        const float m = __fadd_rn(__fmul_rn(re, re), __fmul_rn(im, im));
+#pragma clang fp contract(off)
+        const float m = re * re + im * im;  // two rounded products, one rounded sum
         if (m > v) {  // a thread visits its samples in increasing order
             v = m;
             i = k;
@@ -482,10 +485,14 @@ struct PeakAcc {
     }
 };
 
-__device__ void peak_store(PeakAcc a, const ReqArg& q, int t, int tid)
+// `lds`: 12 words of the kernel's dynamic LDS that no thread reads any more
+// (the kernel keeps no static LDS, so its dynamic limit can be raised to the
+// full 160 KB).
+__device__ void peak_store(PeakAcc a, const ReqArg& q, int t, int tid, float* lds)
 {
-    __shared__ float sv[kUpThreads / 64];
-    __shared__ int si[kUpThreads / 64], sc[kUpThreads / 64];
+    float* sv = lds;
+    int* si = reinterpret_cast<int*>(lds + kUpThreads / 64);
+    int* sc = si + kUpThreads / 64;
     for (int off = 32; off >= 1; off >>= 1)
         a.merge(__shfl_xor(a.v, off), __shfl_xor(a.i, off), __shfl_xor(a.cnt, off));
     if ((tid & 63) == 0) {
@@ -534,7 +541,7 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
             if (zrow) zrow[k] = v;
             if (peaks) acc.add(v.x, v.y, k, q.thr2);
         }
-        if (peaks) peak_store(acc, q, t, tid);
+        if (peaks) peak_store(acc, q, t, tid, sm);  // this path uses no other LDS
         return;
     }
 
@@ -622,7 +629,7 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
             }
         }
     }
-    if (peaks) peak_store(acc, q, t, tid);
+    if (peaks) peak_store(acc, q, t, tid, sm);  // after the last phase's barrier
 }
 
 // ---------------------------------------------------------------------------
@@ -643,9 +650,18 @@ __global__ void k_prep(const c64* __restrict__ a, const c64* __restrict__ b, int
         pr = npr; pi = npi;
         qr = nqr; qi = nqi;
     }
-    fa[i] = c32{ar, ai};
-    fb[i] = c32{(float)bv.x, (float)bv.y};
-    fdc[i] = c32{(float)(pr - qr), (float)(pi - qi)};
+    const float dcr = (float)(pr - qr), dci = (float)(pi - qi);
+    if (i & 1) {
+        // odd lane (slots of a workgroup are lane-contiguous and L is even):
+        // tables for the swapped state (Im y, Re y)
+        fa[i] = c32{ar, -ai};
+        fb[i] = c32{(float)bv.y, (float)bv.x};
+        fdc[i] = c32{dcr, -dci};
+    } else {
+        fa[i] = c32{ar, ai};
+        fb[i] = c32{(float)bv.x, (float)bv.y};
+        fdc[i] = c32{dcr, dci};
+    }
 }
 
 __global__ void k_fill(uint32_t* p, int64_t words)
