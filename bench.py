@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--filters-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--carry-chunk", type=int, default=0)
+    ap.add_argument("--time-chunks", type=int, default=0,
+                    help="split every block in time into this many chunks (small banks)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_compensated"])
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate lane packings first and use the fastest")
@@ -342,10 +344,11 @@ def main():
                                carry_chunk=args.carry_chunk)
         args.filters_per_lane = tuned["filters_per_lane"]
         args.waves_per_group = tuned["waves_per_group"]
+        args.time_chunks = tuned.get("time_chunks", 1)
     stream = torch.cuda.Stream()
     bank = S.Bank(tb, block, stream=stream, precision=args.precision,
                   carry_chunk=args.carry_chunk, filters_per_lane=args.filters_per_lane,
-                  waves_per_group=args.waves_per_group)
+                  waves_per_group=args.waves_per_group, time_chunks=args.time_chunks)
     z = torch.zeros((T, block), dtype=torch.complex64, device="cuda")
     fs_block = tb.filter_samples_per_block(block)
     flops = W.algorithmic_flops(tb, block)
@@ -444,6 +447,7 @@ def main():
             "filters_per_lane": plan["filters_per_lane"],
             "lanes_per_group": plan["lanes_per_group"],
             "carry_chunk": plan["carry_chunk"],
+            "time_chunks": plan["time_chunks"],
         },
         "real_time_templates": T * block_s / (ms_step * 1e-3),
         "block_latency_ms": {"p50": float(np.percentile(lat, 50)),
@@ -467,7 +471,8 @@ def main():
     }
     if tuned is not None:
         out["autotune"] = {"picked": {"filters_per_lane": tuned["filters_per_lane"],
-                                      "waves_per_group": tuned["waves_per_group"]},
+                                      "waves_per_group": tuned["waves_per_group"],
+                                      "time_chunks": tuned.get("time_chunks", 1)},
                            "candidates": tuned["candidates"]}
     if tuned_block is not None:
         out["autotune_block"] = tuned_block

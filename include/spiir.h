@@ -91,6 +91,18 @@ enum {
  *   waves_per_group       wave64s per workgroup in [1, 16] ([1, 8] when
  *                         filters_per_lane is 8); 0 = default.
  *   device                HIP device ordinal the bank lives on.
+ *   time_chunks           P in {0, 1, 2, 4, ..., 64}; 0 or 1 = off.  With
+ *                         P > 1 each block is also split in time, so banks
+ *                         too small to fill the device finish sooner: every
+ *                         band's samples are cut at absolute multiples of a
+ *                         chunk length (a multiple of C, about the block /
+ *                         P); an end-state pass runs all chunks but the last
+ *                         at once from zero state, a chain pass turns those
+ *                         end states into each chunk's start state with
+ *                         a1^length (computed in FP64 at create), and the
+ *                         filter pass runs every chunk from its start state.
+ *                         Results differ from P = 1 by rounding only (the
+ *                         bitwise block-split invariance holds for P <= 1).
  */
 typedef struct {
     int32_t n_templates;
@@ -110,6 +122,7 @@ typedef struct {
     int32_t filters_per_lane;
     int32_t waves_per_group;
     int32_t device;
+    int32_t time_chunks;
 } spiir_bank_desc;
 
 #define SPIIR_MAX_BANDS 12
@@ -281,6 +294,7 @@ typedef struct {
     int32_t lds_bytes;        /* dynamic LDS of the filter kernel              */
     int32_t carry_chunk;      /* C                                             */
     size_t footprint;         /* device bytes spiir_create allocates           */
+    int32_t time_chunks;      /* P (1 = no time split)                         */
 } spiir_plan_info;
 
 int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info);

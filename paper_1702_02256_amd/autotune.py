@@ -1,7 +1,8 @@
 """Autotuner for the filter-bank launch shape and the serving block length.
 
 ``tune_packing`` times every valid (filters_per_lane F, waves_per_group W)
-candidate on the device for a bank shape and keeps the fastest; results are
+candidate on the device for a bank shape (for banks too small to fill the
+device, also with the block split in time) and keeps the fastest; results are
 cached in a JSON file keyed by the GPU architecture and a signature of the
 bank shape (filters per band, largest delay per band, templates, block).
 ``tune_block`` picks the shortest block length whose throughput reaches a
@@ -18,6 +19,11 @@ import os
 import time
 
 DEFAULT_CANDIDATES = [(2, 4), (2, 8), (4, 4), (4, 8), (8, 4)]
+# banks with fewer lanes than this cannot fill the device with filters alone;
+# for them the tuner also tries splitting each block in time
+SMALL_BANK_LANES = 65536
+SMALL_BANK_CANDIDATES = [(1, 1, 1), (1, 2, 1), (4, 1, 1), (1, 1, 16), (1, 2, 32), (4, 1, 16),
+                         (4, 1, 64), (1, 1, 64)]
 CACHE_ENV = "SPIIR_TUNE_CACHE"
 
 
@@ -92,18 +98,26 @@ def tune_packing(tables, block: int, candidates=None, steps: int = 3, use_cache:
     if key in cache:
         return dict(cache[key], cached=True)
     results = []
-    for F, Wv in (candidates or DEFAULT_CANDIDATES):
+    if candidates is None:
+        candidates = list(DEFAULT_CANDIDATES)
+        if tables.total_filters / 4 < SMALL_BANK_LANES:
+            candidates += SMALL_BANK_CANDIDATES
+    for cand in candidates:
+        F, Wv = cand[0], cand[1]
+        P = cand[2] if len(cand) > 2 else 1
+        kw = dict(bank_kw, filters_per_lane=F, waves_per_group=Wv, time_chunks=P)
         try:
-            S.spiir_plan(tables, block, filters_per_lane=F, waves_per_group=Wv, **bank_kw)
+            S.spiir_plan(tables, block, **kw)
         except S.SpiirError:
             continue
-        ms = time_bank(tables, block, steps=steps, filters_per_lane=F, waves_per_group=Wv, **bank_kw)
-        results.append({"filters_per_lane": F, "waves_per_group": Wv, "ms": ms})
+        ms = time_bank(tables, block, steps=steps, **kw)
+        results.append({"filters_per_lane": F, "waves_per_group": Wv, "time_chunks": P, "ms": ms})
     if not results:
         raise RuntimeError("no valid launch shape for this bank")
     best = min(results, key=lambda r: r["ms"])
     out = {"filters_per_lane": best["filters_per_lane"], "waves_per_group": best["waves_per_group"],
-           "ms_per_block": best["ms"], "candidates": results, "tuned_at": time.time()}
+           "time_chunks": best["time_chunks"], "ms_per_block": best["ms"], "candidates": results,
+           "tuned_at": time.time()}
     if use_cache:
         cache = _load_cache()
         cache[key] = out
@@ -130,7 +144,8 @@ def tune_block(tables, blocks=(256, 512, 1024, 2048, 4096), target: float = 0.9,
 def tuned_bank_kwargs(tables, block: int, **bank_kw) -> dict:
     """Bank keyword arguments with the tuned launch shape filled in."""
     t = tune_packing(tables, block, **bank_kw)
-    return dict(bank_kw, filters_per_lane=t["filters_per_lane"], waves_per_group=t["waves_per_group"])
+    return dict(bank_kw, filters_per_lane=t["filters_per_lane"], waves_per_group=t["waves_per_group"],
+                time_chunks=t.get("time_chunks", 1))
 
 
 __all__ = ["tune_packing", "tune_block", "tuned_bank_kwargs", "signature", "time_bank"]

@@ -18,7 +18,7 @@ using namespace spiir;
 namespace {
 
 constexpr int kDefaultF = 4;
-constexpr int kDefaultW = 4;
+constexpr int kDefaultW = 8;
 constexpr int kDefaultC = 32;
 constexpr int kSubBlock = 512;      // samples per LDS window restage
 constexpr int kXcapMax = 24576;     // LDS window, floats
@@ -36,6 +36,8 @@ int64_t next_pow2(int64_t v)
 struct Plan {
     int T = 0, H = 0, L = 0, F = 0, W = 0, C = 0, precision = 0;
     int td = 0, tu = 0, hu_len = 0, max_block = 0, mb_inner = 0;
+    int P = 1;
+    int lc[SPIIR_MAX_BANDS] = {};
     int xcap = 0;
     int nrun_max = 1, npiece_max = 1;
     int lds_filter = 0, lds_stage = 0, lds_up = 0;
@@ -76,6 +78,8 @@ int validate(const spiir_bank_desc* d)
     const int W = d->waves_per_group ? d->waves_per_group : kDefaultW;
     if (W < 1 || 64 * W > filter_max_threads(F)) return SPIIR_EINVAL;
     if (d->device < 0) return SPIIR_EINVAL;
+    if (d->time_chunks < 0 || d->time_chunks > 64 || (d->time_chunks & (d->time_chunks - 1)) != 0)
+        return SPIIR_EINVAL;
     int64_t total = 0;
     for (int64_t s = 0; s < (int64_t)d->n_templates * H; ++s) {
         if (d->n_filters[s] < 0) return SPIIR_EINVAL;
@@ -117,6 +121,14 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
     p.td = p.H > 1 ? d->n_taps_down : 1;
     p.tu = p.H > 1 ? d->n_taps_up : 1;
     p.hu_len = (p.tu + 1) / 2;
+    p.P = d->time_chunks > 1 ? d->time_chunks : 1;
+    // chunk length per band: a multiple of C covering the band's share of the
+    // largest launch in P pieces, so a block meets at most P + 1 chunks
+    for (int h = 0; h < p.H; ++h) {
+        const int mbh = std::max(p.mb_inner >> h, 1);
+        const int per = (mbh + p.P - 1) / p.P;
+        p.lc[h] = std::max(p.C, (per + p.C - 1) / p.C * p.C);
+    }
     const int T = p.T, H = p.H, L = p.L, F = p.F;
 
     std::vector<int64_t> moff((size_t)T * H);
@@ -347,6 +359,8 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
     fp += (size_t)p.zw_elems * sizeof(c32);
     fp += (size_t)T * H * p.hu_len * sizeof(c32) + (size_t)T * sizeof(int32_t) + sizeof(BankDev);
     fp += 2 * sizeof(int64_t);
+    if (p.P > 1)  // a1^lc, end states, chained states, entering chunk-start state, exponents
+        fp += (size_t)p.n_slots * sizeof(c32) * (1 + 2 * (size_t)(p.P + 1) + 1);
     p.footprint = fp;
     return SPIIR_OK;
 }
@@ -413,6 +427,7 @@ struct spiir_bank {
     c32* uphist = nullptr;
     int32_t* flags = nullptr;
     int64_t* clock = nullptr;
+    c32 *al = nullptr, *uend = nullptr, *schain = nullptr, *ys0 = nullptr;
     BankDev* bd = nullptr;
 };
 
@@ -430,7 +445,7 @@ void free_bank(spiir_bank* b)
 {
     if (!b) return;
     void* ptrs[] = {b->a,     b->b,     b->dc, b->y,  b->ys, b->off, b->wg,     b->piece, b->seg,
-                    b->lane_meta, b->rings, b->hd, b->hu, b->zw, b->uphist, b->flags, b->clock, b->bd};
+                    b->lane_meta, b->rings, b->hd, b->hu, b->zw, b->uphist, b->flags, b->clock, b->al, b->uend, b->schain, b->ys0, b->bd};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (b->ev) (void)hipEventDestroy(b->ev);
@@ -529,51 +544,81 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
             ra.H = p.H;
             ra.c0 = (int32_t)c0;
             ra.thr2 = thr2;
+            ra.nchunk = p.P > 1 ? p.P + 1 : 1;
             lds_f = std::max(lds_f, p.lds_filter);
             lds_s = std::max(lds_s, p.lds_stage);
             lds_u = std::max(lds_u, p.lds_up);
             maxH = std::max(maxH, p.H);
         }
-        // filter workgroups: band-major across requests (longest bands first)
-        A.cum[0] = 0;
-        for (int h = 0; h < maxH; ++h)
+        // filter workgroups: band-major across requests (longest bands first),
+        // chunk-major inside a (band, request) segment when split in time
+        auto segments = [&](LaunchArgs& X, bool split_only) {
+            int total = 0;
+            X.nseg = 0;
+            X.cum[0] = 0;
+            for (int h = 0; h < maxH; ++h)
+                for (int k = 0; k < X.nreq; ++k) {
+                    const Plan& p = req[rmap[k]].bank->plan;  // X keeps A's request order
+                    if (h >= p.H) continue;
+                    if (split_only && X.req[k].nchunk == 1) continue;
+                    const int cnt = (p.band_wg0[h + 1] - p.band_wg0[h]) * X.req[k].nchunk;
+                    if (cnt == 0) continue;
+                    X.seg_req[X.nseg] = (int16_t)k;
+                    X.seg_band[X.nseg] = (int16_t)h;
+                    X.cum[X.nseg + 1] = X.cum[X.nseg] + cnt;
+                    X.nseg++;
+                    total += cnt;
+                }
+            return total;
+        };
+        nwg = segments(A, false);
+        // time split: end-state pass (A1) and chain pass (A2) over the split requests
+        LaunchArgs A1, A2;
+        int nwg1 = 0, lds_1 = 0;
+        int64_t nchain = 0;
+        bool split = false;
+        for (int k = 0; k < A.nreq; ++k) split |= A.req[k].nchunk > 1;
+        if (split) {
+            A1 = A;
+            nwg1 = segments(A1, true);
+            std::memset(&A2, 0, sizeof(A2));
             for (int k = 0; k < A.nreq; ++k) {
+                if (A.req[k].nchunk == 1) continue;
                 const Plan& p = req[rmap[k]].bank->plan;
-                if (h >= p.H) continue;
-                const int cnt = p.band_wg0[h + 1] - p.band_wg0[h];
-                if (cnt == 0) continue;
-                A.seg_req[A.nseg] = (int16_t)k;
-                A.seg_band[A.nseg] = (int16_t)h;
-                A.cum[A.nseg + 1] = A.cum[A.nseg] + cnt;
-                A.nseg++;
-                nwg += cnt;
+                lds_1 = std::max(lds_1, p.lds_filter);
+                A2.req[A2.nreq] = A.req[k];
+                A2.cum[A2.nreq + 1] = A2.cum[A2.nreq] + (int32_t)((p.n_slots + 255) / 256);
+                A2.nreq++;
             }
+            nchain = A2.cum[A2.nreq];
+        }
         A.tcum[0] = 0;
         for (int k = 0; k < A.nreq; ++k) {
             A.tcum[k + 1] = A.tcum[k] + req[rmap[k]].bank->plan.T;
             ntm += req[rmap[k]].bank->plan.T;
         }
 
+        // kernel timing: kind 0 staging, kind 1 the filter bank (with the
+        // time-split passes), kind 2 upsample-and-add
         hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        auto mark = [&](int i) {
+            if (!prof) return;
+            ev[i] = prof_event();
+            if (ev[i]) (void)hipEventRecord(ev[i], s);
+        };
+        mark(0);
+        e = (hipError_t)launch_stage(A, lds_s, s);
+        mark(1);
+        if (e == hipSuccess && split && nwg1 > 0)
+            e = (hipError_t)launch_filter_local(F, prec, A1, nwg1, L, lds_1, s);
+        if (e == hipSuccess && split && nchain > 0) e = (hipError_t)launch_chain(A2, nchain, s);
+        if (e == hipSuccess && nwg > 0) e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
+        mark(2);
+        if (e == hipSuccess) e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
+        mark(3);
         if (prof)
-            for (int i = 0; i < 4; ++i) {
-                ev[i] = prof_event();
-                if (ev[i]) (void)hipEventRecord(ev[i], s);
-                if (i == 0) e = (hipError_t)launch_stage(A, lds_s, s);
-                else if (i == 1 && e == hipSuccess && nwg > 0)
-                    e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
-                else if (i == 2 && e == hipSuccess)
-                    e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
-            }
-        else {
-            e = (hipError_t)launch_stage(A, lds_s, s);
-            if (e == hipSuccess && nwg > 0) e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
-            if (e == hipSuccess) e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
-        }
-        if (prof) {
             for (int i = 0; i < 3; ++i)
                 if (ev[i] && ev[i + 1]) g_prof_recs.push_back(ProfRec{i, ev[i], ev[i + 1]});
-        }
     }
     return e;
 }
@@ -644,6 +689,7 @@ int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info)
     info->lds_bytes = p.lds_filter;
     info->carry_chunk = p.C;
     info->footprint = p.footprint;
+    info->time_chunks = p.P;
     return SPIIR_OK;
 }
 
@@ -705,6 +751,12 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     ok &= dalloc(&b->uphist, (size_t)p.T * p.H * p.hu_len) == hipSuccess;
     ok &= dalloc(&b->flags, p.T) == hipSuccess;
     ok &= dalloc(&b->clock, 2) == hipSuccess;
+    if (p.P > 1) {
+        ok &= dalloc(&b->al, p.n_slots) == hipSuccess;
+        ok &= dalloc(&b->uend, (size_t)(p.P + 1) * p.n_slots) == hipSuccess;
+        ok &= dalloc(&b->schain, (size_t)(p.P + 1) * p.n_slots) == hipSuccess;
+        ok &= dalloc(&b->ys0, p.n_slots) == hipSuccess;
+    }
     ok &= dalloc(&b->bd, 1) == hipSuccess;
     ok &= hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
@@ -770,6 +822,13 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     bd.uphist = b->uphist;
     bd.flags = b->flags;
     bd.clock = b->clock;
+    bd.P = p.P;
+    for (int h = 0; h < p.H; ++h) bd.lc[h] = p.lc[h];
+    bd.n_slots = p.n_slots;
+    bd.al = b->al;
+    bd.uend = b->uend;
+    bd.schain = b->schain;
+    bd.ys0 = b->ys0;
 
     hipError_t e = hipSuccess;
     auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -783,6 +842,23 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
         free_bank(b);
         return SPIIR_ENOMEM;
     }
+    // time split: per-slot exponent of a1^lc (the slot's band chunk length)
+    int32_t* dlc = nullptr;
+    std::vector<int32_t> hlc;
+    if (p.P > 1) {
+        hlc.resize((size_t)p.n_slots);
+        const int64_t per_wg = (int64_t)p.F * p.L;
+        for (size_t w = 0; w < p.wg.size(); ++w)
+            for (int64_t i = 0; i < per_wg; ++i) hlc[w * per_wg + i] = p.lc[p.wg[w].band];
+        if (hipMalloc((void**)&dlc, sizeof(int32_t) * std::max<int64_t>(p.n_slots, 1)) != hipSuccess) {
+            (void)hipFree(da);
+            (void)hipFree(db);
+            (void)hipGetLastError();
+            free_bank(b);
+            return SPIIR_ENOMEM;
+        }
+        up(dlc, hlc.data(), sizeof(int32_t) * p.n_slots);
+    }
     up(da, ha.data(), sizeof(c64) * p.n_slots);
     up(db, hb.data(), sizeof(c64) * p.n_slots);
     up(b->off, p.slot_off.data(), sizeof(int32_t) * p.n_slots);
@@ -793,11 +869,13 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     up(b->hd, hd.data(), sizeof(float) * p.td);
     up(b->hu, hu.data(), sizeof(float) * p.tu);
     up(b->bd, &bd, sizeof(BankDev));
-    if (e == hipSuccess) e = (hipError_t)launch_prep(da, db, p.n_slots, p.C, b->a, b->b, b->dc, s);
+    if (e == hipSuccess)
+        e = (hipError_t)launch_prep(da, db, p.n_slots, p.C, b->a, b->b, b->dc, dlc, b->al, s);
     if (e == hipSuccess) e = (hipError_t)zero_state(b, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(da);
     (void)hipFree(db);
+    if (dlc) (void)hipFree(dlc);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_bank(b);

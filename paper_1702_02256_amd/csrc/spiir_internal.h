@@ -29,6 +29,9 @@ constexpr int kSlotNone = 0xffff;
 // Largest workgroup of the filter kernel for F filters per lane: with 8
 // filters a lane needs more than 128 VGPRs, so at most 2 waves per SIMD.
 constexpr int filter_max_threads(int F) { return F >= 8 ? 512 : 1024; }
+// Waves per SIMD the compiler must leave room for (caps VGPRs at 512 / n):
+// with 4 filters a lane fits in 96 VGPRs without spilling, so 5 waves.
+constexpr int filter_min_waves(int F) { return F == 4 ? 5 : 1; }
 
 struct alignas(8) c32 {
     float x, y;
@@ -99,6 +102,15 @@ struct BankDev {
     // filtered; [1]: samples staged so far.  The staging kernel advances them,
     // so a recorded launch sequence can be replayed block after block.
     int64_t* clock;
+    // Parallel-in-time split (P > 1): band h's samples are cut at absolute
+    // multiples of lc[h] (a multiple of C) into at most P + 1 chunks per block.
+    int32_t P;
+    int32_t lc[kMaxBands];
+    int64_t n_slots;
+    const c32* al;                  // per slot: a1^lc (FP64 -> FP32), same form as `a`
+    c32* uend;                      // [P+1][n_slots] chunk end states from zero start
+    c32* schain;                    // [P+1][n_slots] chained chunk start states
+    c32* ys0;                       // [n_slots] chunk-start state entering the block
 };
 
 struct ReqArg {
@@ -111,6 +123,7 @@ struct ReqArg {
     int32_t H;
     int32_t c0;          // offset of this chunk in the caller's block
     float thr2;          // threshold^2 of the trigger count
+    int32_t nchunk;      // time-chunk slots per workgroup (1, or P + 1)
 };
 
 // Everything one launch sequence needs, passed by value as kernel arguments.
@@ -130,7 +143,10 @@ int launch_filter(int F, int precision, const LaunchArgs& a, int nblocks, int L,
                   void* stream);
 int launch_upadd(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream);
 int launch_prep(const c64* a, const c64* b, int64_t n, int C, c32* fa, c32* fb, c32* fdc,
-                void* stream);
+                const int32_t* slot_lc, c32* fal, void* stream);
+int launch_filter_local(int F, int precision, const LaunchArgs& a, int nblocks, int L, int lds_bytes,
+                        void* stream);
+int launch_chain(const LaunchArgs& a, int64_t nblocks, void* stream);
 int launch_fill(void* p, int64_t bytes, void* stream);
 int filter_max_lds();
 int allow_filter_lds();

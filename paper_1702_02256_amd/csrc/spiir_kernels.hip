@@ -116,7 +116,7 @@ __device__ __forceinline__ void lane_sum(float (&vr)[F], float (&vi)[F])
 // conj): the same arithmetic then advances the swapped state.  So every
 // lane's first component sum is what it keeps (even: Re, odd: Im) and its
 // second is what its partner needs, and the pair combine is one DPP add.
-template <int F>
+template <int F, bool SUM>
 __device__ __forceinline__ void one_step(const float (&xv)[F], float* __restrict__ pcol, int j,
                                          const float (&ar)[F],
                                          const float (&ai)[F], const float (&br)[F],
@@ -131,6 +131,7 @@ __device__ __forceinline__ void one_step(const float (&xv)[F], float* __restrict
         yr[f] = nr; yi[f] = ni;
         tr[f] = nr; ti[f] = ni;
     }
+    if (!SUM) return;  // end-state pass of a time split: no output
     lane_sum<F>(tr, ti);
     // even lane: re_even + re_odd; odd lane: im_odd + im_even
     pcol[2 * j] = tr[0] + pair_swap(ti[0]);
@@ -141,7 +142,7 @@ __device__ __forceinline__ void one_step(const float (&xv)[F], float* __restrict
 // in the window copy of its delay's parity, so one ds_read_b64 feeds two
 // samples.  The restrict qualifiers tell the compiler that the partial-sum
 // stores never alias the window, so later loads can be issued ahead of them.
-template <int F>
+template <int F, bool SUM>
 __device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* __restrict__ pcol,
                                           const float (&ar)[F],
                                           const float (&ai)[F], const float (&br)[F],
@@ -159,14 +160,14 @@ __device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* _
             xa[f] = v.x;
             xb[f] = v.y;
         }
-        one_step<F>(xa, pcol, 2 * jj, ar, ai, br, bi, yr, yi);
-        one_step<F>(xb, pcol, 2 * jj + 1, ar, ai, br, bi, yr, yi);
+        one_step<F, SUM>(xa, pcol, 2 * jj, ar, ai, br, bi, yr, yi);
+        one_step<F, SUM>(xb, pcol, 2 * jj + 1, ar, ai, br, bi, yr, yi);
     }
 }
 
 // `cnt` samples from arbitrary starting points: x1[f] points at x[k - d] in the
 // unshifted window copy.
-template <int F>
+template <int F, bool SUM>
 __device__ __forceinline__ void tile_partial(const float* const (&xp)[F], int cnt,
                                              float* __restrict__ pcol, const float (&ar)[F], const float (&ai)[F],
                                              const float (&br)[F], const float (&bi)[F],
@@ -176,12 +177,47 @@ __device__ __forceinline__ void tile_partial(const float* const (&xp)[F], int cn
         float xv[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) xv[f] = xp[f][j];
-        one_step<F>(xv, pcol, j, ar, ai, br, bi, yr, yi);
+        one_step<F, SUM>(xv, pcol, j, ar, ai, br, bi, yr, yi);
     }
 }
 
-template <int F, bool COMP>
-__global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs args)
+// Time chunk c of a band's block [s0h, s0h + nh) when the bank is split in
+// time: chunk 0 runs from the block start to the first absolute multiple of
+// lc, chunk c >= 1 covers [B + (c-1) lc, B + c lc) clipped to the block.
+struct Chunk {
+    int k0, k1;       // block-relative sample range (empty if k0 >= k1)
+    bool first, last; // first / last non-empty chunk of the block
+};
+
+__device__ __forceinline__ Chunk chunk_range(int c, int nchunk, int64_t s0h, int nh, int lc)
+{
+    Chunk r;
+    if (nchunk == 1) {
+        r.k0 = 0;
+        r.k1 = nh;
+        r.first = r.last = true;
+        return r;
+    }
+    const int64_t B = (s0h + lc - 1) / lc * lc;
+    const int first_c = B == s0h ? 1 : 0;
+    const int last_c = s0h + nh - 1 < B ? 0 : 1 + (int)((s0h + nh - 1 - B) / lc);
+    int64_t cs = c == 0 ? s0h : B + (int64_t)(c - 1) * lc;
+    int64_t ce = c == 0 ? B : cs + lc;
+    if (cs < s0h) cs = s0h;
+    if (ce > s0h + nh) ce = s0h + nh;
+    r.k0 = (int)(cs - s0h);
+    r.k1 = ce > cs ? (int)(ce - s0h) : r.k0;
+    r.first = c == first_c;
+    r.last = c == last_c;
+    return r;
+}
+
+// LOCAL: the end-state pass of a time split (every chunk but the last runs
+// from zero, or the first from the carried state, and stores its end state;
+// no output).  Otherwise: the filter pass proper, each chunk starting from its
+// chained state.
+template <int F, bool COMP, bool LOCAL>
+__global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F)) k_filter(LaunchArgs args)
 {
     extern __shared__ float sm[];
     const int bid = blockIdx.x;
@@ -194,11 +230,16 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
     const ReqArg& q = args.req[args.seg_req[lo]];
     const int h = args.seg_band[lo];
     const BankDev* bd = q.bd;
-    const WgDesc wg = bd->wg[bd->band_wg0[h] + (bid - args.cum[lo])];
+    const int nwg_h = bd->band_wg0[h + 1] - bd->band_wg0[h];
+    const int li = bid - args.cum[lo];
+    const int tc = li / nwg_h;  // time chunk (chunk-major order)
+    const WgDesc wg = bd->wg[bd->band_wg0[h] + (li - tc * nwg_h)];
     const int L = blockDim.x;
     const int tid = threadIdx.x;
     const int nh = q.n >> h;
     const int64_t s0h = bd->clock[0] >> h;  // set by the staging kernel of this chunk
+    const Chunk ch = chunk_range(tc, q.nchunk, s0h, nh, bd->lc[h]);
+    if (ch.k0 >= ch.k1 || (LOCAL && ch.last)) return;  // whole workgroup
     const int64_t cmask = bd->C - 1;
     const int nrun = bd->nrun_max;
 
@@ -221,10 +262,30 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
 
     float ar[F], ai[F], br[F], bi[F], dr[F], di[F], yr[F], yi[F], sr[F], si[F];
     int dl[F];
+    // Start state.  The first chunk starts from the carried state; when the
+    // block has more than one chunk, the end-state pass saves that state
+    // (schain row of the first chunk, ys0) for the filter pass, whose last
+    // chunk overwrites the carried state while the first may still read it.
+    // A later chunk starts from zero in the end-state pass and from its chained
+    // state in the filter pass (its start is a carry-chunk boundary, so y and
+    // the chunk-start state agree).
+    const c32* ysrc = bd->y;
+    const c32* yssrc = bd->ys;
+    if (!ch.first) ysrc = yssrc = bd->schain + (int64_t)tc * bd->n_slots;
+    else if (!LOCAL && !ch.last) {
+        ysrc = bd->schain + (int64_t)tc * bd->n_slots;
+        yssrc = bd->ys0;
+    }
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int64_t g = wg.slot_base + (int64_t)f * L + tid;
-        const c32 a = bd->a[g], b = bd->b[g], d = bd->dc[g], y = bd->y[g], ys = bd->ys[g];
+        c32 y = ysrc[g], ys = yssrc[g];
+        if (LOCAL && !ch.first) y = ys = c32{0.0f, 0.0f};
+        if (LOCAL && ch.first) {
+            bd->schain[(int64_t)tc * bd->n_slots + g] = y;
+            bd->ys0[g] = ys;
+        }
+        const c32 a = bd->a[g], b = bd->b[g], d = bd->dc[g];
         ar[f] = a.x; ai[f] = a.y;
         br[f] = b.x; bi[f] = b.y;
         dr[f] = d.x; di[f] = d.y;
@@ -258,8 +319,8 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
     float* pcol = reinterpret_cast<float*>(pbuf + pe * (kTile + 1)) + (tid & 1);
     int parity = 0;
 
-    for (int kb = 0; kb < nh; kb += S) {
-        const int sub = min(S, nh - kb);
+    for (int kb = ch.k0; kb < ch.k1; kb += S) {
+        const int sub = min(S, ch.k1 - kb);
         // window start: a multiple of 64 at or below the oldest sample any filter
         // reads, minus one, so that an odd-delay pair never starts before E1[0]
         const int64_t origin = ((s0h + kb - wg.maxd - 1) >> 6) << 6;
@@ -285,12 +346,12 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
                     const int par = dl[f] & 1;
                     xp[f] = reinterpret_cast<const float2*>((par ? E1 : E0) + (rel - dl[f] - par));
                 }
-                tile_full<F>(xp, pcol, ar, ai, br, bi, yr, yi);
+                tile_full<F, !LOCAL>(xp, pcol, ar, ai, br, bi, yr, yi);
             } else {
                 const float* xp[F];
 #pragma unroll
                 for (int f = 0; f < F; ++f) xp[f] = E0 + (rel - dl[f]);
-                tile_partial<F>(xp, cnt, pcol, ar, ai, br, bi, yr, yi);
+                tile_partial<F, !LOCAL>(xp, cnt, pcol, ar, ai, br, bi, yr, yi);
             }
 
             // carry correction after the last sample of an absolute chunk of C samples
@@ -304,91 +365,93 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
                 }
             }
 
-            // Level 1 reads only partials written by the thread's own wave (its
-            // 16-lane group lies inside the wave), so a wave-local sync suffices.
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            c32* l2 = l2buf + parity * (kTile * nrun);
-            // level 1: each thread sums one sample row over the runs of a 16-lane group
-            // (all 16 partials are loaded before any run result is stored)
-            if (j1 < cnt) {
-                constexpr int kPairs = kRunLanes / 2;
-                const int e0 = q1 * kPairs;
-                const c32* grp = pbuf + e0 * (kTile + 1) + j1;
-                c32 v[kPairs];
-#pragma unroll
-                for (int i = 0; i < kPairs; ++i) v[i] = grp[i * (kTile + 1)];
-                c32* out = l2 + j1 * nrun;
-                if (endmask == (1u << (kPairs - 1))) {
-                    // the whole group is one run
-                    float accr = v[0].x, acci = v[0].y, er = 0.0f, ei = 0.0f;
-#pragma unroll
-                    for (int i = 1; i < kPairs; ++i) {
-                        if (COMP) {
-                            float e1, e2;
-                            two_sum(accr, v[i].x, accr, e1);
-                            two_sum(acci, v[i].y, acci, e2);
-                            er += e1;
-                            ei += e2;
-                        } else {
-                            accr += v[i].x;
-                            acci += v[i].y;
+            if (!LOCAL) {
+                // Level 1 reads only partials written by the thread's own wave (its
+                // 16-lane group lies inside the wave), so a wave-local sync suffices.
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                c32* l2 = l2buf + parity * (kTile * nrun);
+                // level 1: each thread sums one sample row over the runs of a 16-lane group
+                // (all 16 partials are loaded before any run result is stored)
+                if (j1 < cnt) {
+                    constexpr int kPairs = kRunLanes / 2;
+                    const int e0 = q1 * kPairs;
+                    const c32* grp = pbuf + e0 * (kTile + 1) + j1;
+                    c32 v[kPairs];
+    #pragma unroll
+                    for (int i = 0; i < kPairs; ++i) v[i] = grp[i * (kTile + 1)];
+                    c32* out = l2 + j1 * nrun;
+                    if (endmask == (1u << (kPairs - 1))) {
+                        // the whole group is one run
+                        float accr = v[0].x, acci = v[0].y, er = 0.0f, ei = 0.0f;
+    #pragma unroll
+                        for (int i = 1; i < kPairs; ++i) {
+                            if (COMP) {
+                                float e1, e2;
+                                two_sum(accr, v[i].x, accr, e1);
+                                two_sum(acci, v[i].y, acci, e2);
+                                er += e1;
+                                ei += e2;
+                            } else {
+                                accr += v[i].x;
+                                acci += v[i].y;
+                            }
                         }
-                    }
-                    out[slot0] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
-                } else {
-                    int slot = slot0;
-                    float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
-                    bool fresh = true;
-#pragma unroll
-                    for (int i = 0; i < kPairs; ++i) {
-                        if (fresh) {
-                            accr = v[i].x;
-                            acci = v[i].y;
-                            er = 0.0f;
-                            ei = 0.0f;
-                        } else if (COMP) {
-                            float e1, e2;
-                            two_sum(accr, v[i].x, accr, e1);
-                            two_sum(acci, v[i].y, acci, e2);
-                            er += e1;
-                            ei += e2;
-                        } else {
-                            accr += v[i].x;
-                            acci += v[i].y;
-                        }
-                        fresh = (endmask >> i) & 1u;
-                        if (fresh) {
-                            out[slot] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
-                            ++slot;
+                        out[slot0] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
+                    } else {
+                        int slot = slot0;
+                        float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
+                        bool fresh = true;
+    #pragma unroll
+                        for (int i = 0; i < kPairs; ++i) {
+                            if (fresh) {
+                                accr = v[i].x;
+                                acci = v[i].y;
+                                er = 0.0f;
+                                ei = 0.0f;
+                            } else if (COMP) {
+                                float e1, e2;
+                                two_sum(accr, v[i].x, accr, e1);
+                                two_sum(acci, v[i].y, acci, e2);
+                                er += e1;
+                                ei += e2;
+                            } else {
+                                accr += v[i].x;
+                                acci += v[i].y;
+                            }
+                            fresh = (endmask >> i) & 1u;
+                            if (fresh) {
+                                out[slot] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
+                                ++slot;
+                            }
                         }
                     }
                 }
-            }
-            __syncthreads();
-            // level 2: each (piece, sample) sums its runs in order and writes the output
-            for (int task = tid; task < wg.npiece * kTile; task += L) {
-                const int p = task / kTile;
-                const int j = task & (kTile - 1);
-                if (j < cnt) {
-                    const int2 rr = prun[p];
-                    const c32* row = l2 + j * nrun;
-                    float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
-                    for (int s = rr.x; s < rr.y; ++s) {
-                        const c32 v = row[s];
-                        if (COMP) {
-                            float e1, e2;
-                            two_sum(accr, v.x, accr, e1);
-                            two_sum(acci, v.y, acci, e2);
-                            er += e1;
-                            ei += e2;
-                        } else {
-                            accr += v.x;
-                            acci += v.y;
+                __syncthreads();
+                // level 2: each (piece, sample) sums its runs in order and writes the output
+                for (int task = tid; task < wg.npiece * kTile; task += L) {
+                    const int p = task / kTile;
+                    const int j = task & (kTile - 1);
+                    if (j < cnt) {
+                        const int2 rr = prun[p];
+                        const c32* row = l2 + j * nrun;
+                        float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
+                        for (int s = rr.x; s < rr.y; ++s) {
+                            const c32 v = row[s];
+                            if (COMP) {
+                                float e1, e2;
+                                two_sum(accr, v.x, accr, e1);
+                                two_sum(acci, v.y, acci, e2);
+                                er += e1;
+                                ei += e2;
+                            } else {
+                                accr += v.x;
+                                acci += v.y;
+                            }
                         }
+                        bd->zw[pzoff[p] + k + j] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
                     }
-                    bd->zw[pzoff[p] + k + j] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
                 }
             }
             parity ^= 1;
@@ -396,6 +459,13 @@ __global__ void __launch_bounds__(filter_max_threads(F)) k_filter(LaunchArgs arg
         }
     }
 
+    if (LOCAL) {
+        c32* ue = bd->uend + (int64_t)tc * bd->n_slots;
+#pragma unroll
+        for (int f = 0; f < F; ++f) ue[wg.slot_base + (int64_t)f * L + tid] = c32{yr[f], yi[f]};
+        return;
+    }
+    if (!ch.last) return;  // only the block's last chunk carries its state on
     bool bad = false;
 #pragma unroll
     for (int f = 0; f < F; ++f) {
@@ -633,10 +703,58 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
 }
 
 // ---------------------------------------------------------------------------
+// Time split, middle pass: per filter slot, the start state of every chunk
+// after the first, S[c+1] = uend[c] + a1^lc S[c] with S[first+1] = uend[first]
+// (the first chunk's end state, which ran from the carried state).  The
+// product uses the same component formula as the recurrence, so it also holds
+// for the swapped form of odd lanes.  One thread per slot; request r owns
+// blocks [cum[r], cum[r+1]).
+// ---------------------------------------------------------------------------
+constexpr int kChainThreads = 256;
+
+__global__ void __launch_bounds__(kChainThreads) k_chain(LaunchArgs args)
+{
+    const int bid = blockIdx.x;
+    int r = 0;
+    while (r + 1 < args.nreq && args.cum[r + 1] <= bid) ++r;
+    const ReqArg& q = args.req[r];
+    const BankDev* bd = q.bd;
+    const int64_t g = (int64_t)(bid - args.cum[r]) * kChainThreads + threadIdx.x;
+    if (g >= bd->n_slots) return;
+    const int h = bd->wg[g / ((int64_t)bd->F * bd->L)].band;
+    const int nh = q.n >> h, lc = bd->lc[h];
+    const int64_t s0h = bd->clock[0] >> h;
+    const int64_t B = (s0h + lc - 1) / lc * lc;
+    const int first_c = B == s0h ? 1 : 0;
+    const int last_c = s0h + nh - 1 < B ? 0 : 1 + (int)((s0h + nh - 1 - B) / lc);
+    const int64_t ns = bd->n_slots;
+    c32 st = bd->uend[first_c * ns + g];
+    const c32 al = bd->al[g];
+    for (int c = first_c + 1; c <= last_c; ++c) {
+        bd->schain[c * ns + g] = st;
+        if (c < last_c) {
+            const c32 u = bd->uend[c * ns + g];
+            st = c32{fmaf(al.x, st.x, fmaf(-al.y, st.y, u.x)), fmaf(al.x, st.y, fmaf(al.y, st.x, u.y))};
+        }
+    }
+}
+
+int launch_chain(const LaunchArgs& a, int64_t nblocks, void* stream)
+{
+    hipLaunchKernelGGL(k_chain, dim3((unsigned)nblocks), dim3(kChainThreads), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // FP64 carry precompute and FP32 conversion of the tables (once, at create).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ c64 cmul(c64 u, c64 v)
+{
+    return c64{u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x};
+}
+
 __global__ void k_prep(const c64* __restrict__ a, const c64* __restrict__ b, int64_t n, int C,
-                       c32* fa, c32* fb, c32* fdc)
+                       c32* fa, c32* fb, c32* fdc, const int32_t* __restrict__ slot_lc, c32* fal)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -651,16 +769,28 @@ __global__ void k_prep(const c64* __restrict__ a, const c64* __restrict__ b, int
         qr = nqr; qi = nqi;
     }
     const float dcr = (float)(pr - qr), dci = (float)(pi - qi);
+    // a1^lc for the time split, by repeated squaring in FP64
+    c64 al{1.0, 0.0};
+    if (slot_lc) {
+        c64 base = av;
+        for (int e = slot_lc[i]; e > 0; e >>= 1) {
+            if (e & 1) al = cmul(al, base);
+            base = cmul(base, base);
+        }
+    }
+    const float alr = (float)al.x, ali = (float)al.y;
     if (i & 1) {
         // odd lane (slots of a workgroup are lane-contiguous and L is even):
         // tables for the swapped state (Im y, Re y)
         fa[i] = c32{ar, -ai};
         fb[i] = c32{(float)bv.y, (float)bv.x};
         fdc[i] = c32{dcr, -dci};
+        if (fal) fal[i] = c32{alr, -ali};
     } else {
         fa[i] = c32{ar, ai};
         fb[i] = c32{(float)bv.x, (float)bv.y};
         fdc[i] = c32{dcr, dci};
+        if (fal) fal[i] = c32{alr, ali};
     }
 }
 
@@ -680,19 +810,23 @@ int launch_stage(const LaunchArgs& a, int lds_bytes, void* stream)
     return (int)hipGetLastError();
 }
 
-template <int F, bool COMP>
+template <int F, bool COMP, bool LOCAL>
 static int launch_filter_t(const LaunchArgs& a, int nblocks, int L, int lds_bytes,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL((k_filter<F, COMP>), dim3(nblocks), dim3(L), lds_bytes, s, a);
+    hipLaunchKernelGGL((k_filter<F, COMP, LOCAL>), dim3(nblocks), dim3(L), lds_bytes, s, a);
     return (int)hipGetLastError();
 }
 
 template <int F, bool COMP>
 static int allow_lds_t()
 {
-    return (int)hipFuncSetAttribute((const void*)k_filter<F, COMP>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, filter_max_lds());
+    int e = (int)hipFuncSetAttribute((const void*)k_filter<F, COMP, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, filter_max_lds());
+    if (!e)
+        e = (int)hipFuncSetAttribute((const void*)k_filter<F, COMP, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, filter_max_lds());
+    return e;
 }
 
 // Raises the dynamic LDS limit of the filter-kernel variants and the
@@ -713,22 +847,36 @@ int allow_filter_lds()
     return e;
 }
 
+template <bool LOCAL>
+static int launch_filter_any(int F, int precision, const LaunchArgs& a, int nblocks, int L,
+                             int lds_bytes, hipStream_t s)
+{
+    const bool comp = precision == SPIIR_FP32_COMPENSATED;
+    switch (F) {
+    case 1: return comp ? launch_filter_t<1, true, LOCAL>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<1, false, LOCAL>(a, nblocks, L, lds_bytes, s);
+    case 2: return comp ? launch_filter_t<2, true, LOCAL>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<2, false, LOCAL>(a, nblocks, L, lds_bytes, s);
+    case 4: return comp ? launch_filter_t<4, true, LOCAL>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<4, false, LOCAL>(a, nblocks, L, lds_bytes, s);
+    case 8: return comp ? launch_filter_t<8, true, LOCAL>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<8, false, LOCAL>(a, nblocks, L, lds_bytes, s);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
 int launch_filter(int F, int precision, const LaunchArgs& a, int nblocks, int L, int lds_bytes,
                   void* stream)
 {
-    hipStream_t s = (hipStream_t)stream;
-    const bool comp = precision == SPIIR_FP32_COMPENSATED;
-    switch (F) {
-    case 1: return comp ? launch_filter_t<1, true>(a, nblocks, L, lds_bytes, s)
-                        : launch_filter_t<1, false>(a, nblocks, L, lds_bytes, s);
-    case 2: return comp ? launch_filter_t<2, true>(a, nblocks, L, lds_bytes, s)
-                        : launch_filter_t<2, false>(a, nblocks, L, lds_bytes, s);
-    case 4: return comp ? launch_filter_t<4, true>(a, nblocks, L, lds_bytes, s)
-                        : launch_filter_t<4, false>(a, nblocks, L, lds_bytes, s);
-    case 8: return comp ? launch_filter_t<8, true>(a, nblocks, L, lds_bytes, s)
-                        : launch_filter_t<8, false>(a, nblocks, L, lds_bytes, s);
-    default: return (int)hipErrorInvalidValue;
-    }
+    return launch_filter_any<false>(F, precision, a, nblocks, L, lds_bytes, (hipStream_t)stream);
+}
+
+// the end-state pass of a time split (the compensated sum plays no part in it)
+int launch_filter_local(int F, int precision, const LaunchArgs& a, int nblocks, int L, int lds_bytes,
+                        void* stream)
+{
+    (void)precision;
+    return launch_filter_any<true>(F, SPIIR_FP32, a, nblocks, L, lds_bytes, (hipStream_t)stream);
 }
 
 int launch_upadd(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream)
@@ -738,13 +886,13 @@ int launch_upadd(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream)
 }
 
 int launch_prep(const c64* a, const c64* b, int64_t n, int C, c32* fa, c32* fb, c32* fdc,
-                void* stream)
+                const int32_t* slot_lc, c32* fal, void* stream)
 {
     if (n <= 0) return 0;
     const int bs = 256;
     const int64_t nb = (n + bs - 1) / bs;
     hipLaunchKernelGGL(k_prep, dim3((unsigned)nb), dim3(bs), 0, (hipStream_t)stream, a, b, n, C,
-                       fa, fb, fdc);
+                       fa, fb, fdc, slot_lc, fal);
     return (int)hipGetLastError();
 }
 

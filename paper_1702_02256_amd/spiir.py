@@ -51,6 +51,7 @@ class BankDesc(C.Structure):
         ("filters_per_lane", C.c_int32),
         ("waves_per_group", C.c_int32),
         ("device", C.c_int32),
+        ("time_chunks", C.c_int32),
     ]
 
 
@@ -75,6 +76,7 @@ class PlanInfo(C.Structure):
         ("lds_bytes", C.c_int32),
         ("carry_chunk", C.c_int32),
         ("footprint", C.c_size_t),
+        ("time_chunks", C.c_int32),
     ]
 
 
@@ -161,7 +163,7 @@ class _DescHolder:
     """A BankDesc plus the numpy arrays its pointers refer to."""
 
     def __init__(self, tables, max_block, precision="fp32", carry_chunk=0, filters_per_lane=0,
-                 waves_per_group=0, device=0):
+                 waves_per_group=0, device=0, time_chunks=0):
         self.nf = np.ascontiguousarray(tables.n_filters.reshape(-1), dtype=np.int32)
         self.a1 = np.ascontiguousarray(np.asarray(tables.a1, np.complex128)).view(np.float64)
         self.b0 = np.ascontiguousarray(np.asarray(tables.b0, np.complex128)).view(np.float64)
@@ -180,7 +182,7 @@ class _DescHolder:
             n_taps_up=len(self.hu), h_up=dp(self.hu),
             max_block=int(max_block), precision=prec, carry_chunk=int(carry_chunk),
             filters_per_lane=int(filters_per_lane), waves_per_group=int(waves_per_group),
-            device=int(device))
+            device=int(device), time_chunks=int(time_chunks))
 
 
 # ---------------------------------------------------------------- C-named functions
@@ -320,17 +322,17 @@ class Bank:
     """One template bank bound to one input stream (owns its device memory)."""
 
     def __init__(self, tables, max_block, stream=None, precision="fp32", carry_chunk=0,
-                 filters_per_lane=0, waves_per_group=0, device=0):
+                 filters_per_lane=0, waves_per_group=0, device=0, time_chunks=0):
         lib = load_library()
         self._lib = lib
         hold = _DescHolder(tables, max_block, precision, carry_chunk, filters_per_lane,
-                           waves_per_group, device)
+                           waves_per_group, device, time_chunks)
         self.n_templates = int(tables.n_filters.shape[0])
         self.n_bands = int(tables.n_filters.shape[1])
         self.max_block = int(max_block)
         self.plan = spiir_plan(tables, max_block, precision=precision, carry_chunk=carry_chunk,
                                filters_per_lane=filters_per_lane, waves_per_group=waves_per_group,
-                               device=device)
+                               device=device, time_chunks=time_chunks)
         h = C.c_void_p()
         s = _stream_handle(stream) if stream is not None else C.c_void_p(0)
         _check(lib.spiir_create(C.byref(hold.desc), s, C.byref(h)), "spiir_create")

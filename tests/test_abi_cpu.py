@@ -94,6 +94,7 @@ def test_footprint_matches_plan_and_scales():
     ("n_bands", 0), ("n_bands", 13), ("max_block", 0), ("max_block", 1023 + 2),
     ("precision", 7), ("carry_chunk", 48), ("carry_chunk", 8), ("filters_per_lane", 3),
     ("waves_per_group", 17), ("base_rate_hz", 0), ("n_templates", 0), ("device", -1),
+    ("time_chunks", 3), ("time_chunks", 128), ("time_chunks", -1),
 ])
 def test_descriptor_validation(field, value):
     tb = _small_multirate()
@@ -152,3 +153,13 @@ def test_create_without_device_reports_device_error():
     bank = C.c_void_p()
     rc = S.load_library().spiir_create(C.byref(h.desc), None, C.byref(bank))
     assert rc == S.SPIIR_EDEVICE and bank.value is None
+
+
+def test_plan_time_chunks():
+    wl = W.config1()
+    p1 = S.spiir_plan(wl.bank, 4096)
+    p32 = S.spiir_plan(wl.bank, 4096, time_chunks=32)
+    assert p1["time_chunks"] == 1 and p32["time_chunks"] == 32
+    # chunk states and the a1^length table are allocated only for a split bank
+    assert p32["footprint"] > p1["footprint"]
+    assert S.spiir_plan(wl.bank, 4096, time_chunks=1)["footprint"] == p1["footprint"]

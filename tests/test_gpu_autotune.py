@@ -17,7 +17,10 @@ def test_tune_packing_and_block(tmp_path, monkeypatch):
     tb = W.config4(n_templates=64, templates=list(range(64)), n_blocks=1).bank
     t = A.tune_packing(tb, 1024, steps=2)
     assert not t["cached"] and len(t["candidates"]) >= 3
-    assert (t["filters_per_lane"], t["waves_per_group"]) in A.DEFAULT_CANDIDATES
+    tried = {(c["filters_per_lane"], c["waves_per_group"], c["time_chunks"]) for c in t["candidates"]}
+    assert (t["filters_per_lane"], t["waves_per_group"], t["time_chunks"]) in tried
+    # a bank this small also gets the time-split candidates
+    assert any(c[2] > 1 for c in tried)
     assert A.tune_packing(tb, 1024)["cached"]
     b = A.tune_block(tb, blocks=(256, 1024, 4096), steps=2)
     assert b["block"] in (256, 1024, 4096)
