@@ -512,20 +512,6 @@ __device__ __forceinline__ c32 piece_sum(const c32* zw, const SegDesc& sg, int64
     return c32{vr, vi};
 }
 
-__device__ __forceinline__ float4 piece_sum2(const c32* zw, const SegDesc& sg, int64_t stride,
-                                             int k)
-{
-    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int p = 0; p < sg.npiece; ++p) {
-        const float4 u = *reinterpret_cast<const float4*>(zw + sg.zoff + p * stride + k);
-        v.x += u.x;
-        v.y += u.y;
-        v.z += u.z;
-        v.w += u.w;
-    }
-    return v;
-}
-
 // Trigger reduction of one template's block (the step after the filter in the
 // search pipeline, §5): the largest |z|^2, the first sample attaining it and
 // the number of samples at or above a threshold.  |z|^2 is re*re + im*im with
@@ -624,8 +610,9 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
     const c32* hist_in = bd->uphist + ((int64_t)t * H + 1) * HU;
     for (int i = tid; i < (H - 2) * HU; i += kUpThreads) hl[i] = hist_in[i];
 
-    // every other band's own output, both phases per low-rate sample; all of
-    // this block's loads are issued before the first barrier
+    // every other band's own output, both phases per low-rate sample.  The
+    // first piece of every band is loaded for all slots at once (independent
+    // loads, one wait), then the other pieces of split segments are added.
     float4 pv[kUpSlotsTotal];
 #pragma unroll
     for (int h = 0; h < kMaxBands - 1; ++h) {
@@ -633,8 +620,29 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
         for (int i = 0; i < up_slots(h); ++i) {
             pv[up_slot_base(h) + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             const int m = tid + kUpThreads * i;
-            if (h < H - 1 && m < (n >> (h + 1)))
-                pv[up_slot_base(h) + i] = piece_sum2(bd->zw, seg[h], bd->zstride[h], 2 * m);
+            if (h < H - 1 && m < (n >> (h + 1)) && seg[h].npiece > 0)
+                pv[up_slot_base(h) + i] =
+                    *reinterpret_cast<const float4*>(bd->zw + seg[h].zoff + 2 * m);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < kMaxBands - 1; ++h) {
+        if (h >= H - 1) continue;
+        const SegDesc sg = seg[h];
+        for (int p = 1; p < sg.npiece; ++p) {
+#pragma unroll
+            for (int i = 0; i < up_slots(h); ++i) {
+                const int m = tid + kUpThreads * i;
+                if (m < (n >> (h + 1))) {
+                    const float4 u =
+                        *reinterpret_cast<const float4*>(bd->zw + sg.zoff + p * bd->zstride[h] + 2 * m);
+                    float4& v = pv[up_slot_base(h) + i];
+                    v.x += u.x;
+                    v.y += u.y;
+                    v.z += u.z;
+                    v.w += u.w;
+                }
+            }
         }
     }
 
