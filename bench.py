@@ -97,6 +97,7 @@ def cpu_baseline(wl, block: int, budget_s: float, gpu_error_blocks: int = 4):
     sel = np.unique(np.linspace(0, T - 1, ns).round().astype(np.int64))
     sub = wl.bank.subset(sel)
     x = wl.stream()
+    cores = oracle.set_threads(0)
     bank = oracle.OracleBank(sub)
     fs_block = sub.filter_samples_per_block(block)
     done, fs = 0, 0
@@ -114,7 +115,21 @@ def cpu_baseline(wl, block: int, budget_s: float, gpu_error_blocks: int = 4):
             break
     dt = time.perf_counter() - t0
     bank.close()
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    # the same oracle on one thread, on the first templates of the sample
+    n1 = max(1, min(len(sel), 32))
+    sub1 = wl.bank.subset(sel[:n1])
+    oracle.set_threads(1)
+    b1 = oracle.OracleBank(sub1)
+    d1, t1s = 0, time.perf_counter()
+    while (d1 + 1) * block <= len(x):
+        b1.process(x[d1 * block:(d1 + 1) * block])
+        d1 += 1
+        if time.perf_counter() - t1s >= budget_s / 4 and d1 >= 1:
+            break
+    dt1 = time.perf_counter() - t1s
+    b1.close()
+    oracle.set_threads(0)
+    single = sub1.filter_samples_per_block(block) * d1 / dt1
     out = {
         "value": fs / dt,
         "unit": "template-filter-samples/s",
@@ -123,6 +138,8 @@ def cpu_baseline(wl, block: int, budget_s: float, gpu_error_blocks: int = 4):
         "cpu_model": _cpu_model(),
         "sample": f"{len(sel)} of {T} templates (evenly spaced), {done} blocks of {block} "
                   f"samples, FP64 C oracle (gcc -O2, OpenMP over templates), {dt:.2f} s wall",
+        "single_thread_value": single,
+        "single_thread_sample": f"{n1} templates, {d1} blocks, {dt1:.2f} s wall",
     }
     # error of the GPU path on the same sample
     zr = np.concatenate(refs, axis=1)
@@ -450,7 +467,7 @@ def main():
             "time_chunks": plan["time_chunks"],
         },
         "real_time_templates": T * block_s / (ms_step * 1e-3),
-        "block_latency_ms": {"p50": float(np.percentile(lat, 50)),
+        "block_latency_ms": {"mean": float(lat.mean()), "p50": float(np.percentile(lat, 50)),
                              "p99": float(np.percentile(lat, 99)),
                              "kind": "closed loop, back-to-back blocks (GPU time per block)"},
         "fp32_peak_fraction_whole_step": flops["total"] / (ms_step * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,

@@ -49,6 +49,8 @@ def _load():
         lib.oracle_samples_done.restype = i64
         lib.oracle_samples_done.argtypes = [C.c_void_p]
         lib.oracle_filter_one.argtypes = [dp, dp, C.c_int32, dp, dp, i64, dp]
+        lib.oracle_threads.restype = C.c_int
+        lib.oracle_threads.argtypes = [C.c_int]
         lib.oracle_downsample.argtypes = [dp, C.c_int, dp, i64, dp]
         lib.oracle_upsample_add.argtypes = [dp, C.c_int, dp, i64, dp, dp]
         _lib = lib
@@ -164,3 +166,8 @@ def upsample_add(h_up, low, z) -> np.ndarray:
     lib.oracle_upsample_add(_dp(h), len(h), _dp(low.view(np.float64)), len(low),
                             _dp(z.view(np.float64)), _dp(acc.view(np.float64)))
     return acc
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the template loop for timing (0 = all); returns the count in use."""
+    return int(_load().oracle_threads(int(n)))

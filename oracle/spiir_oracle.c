@@ -33,6 +33,7 @@
  *     the block result equals the whole-stream result.
  */
 #include <complex.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -77,6 +78,16 @@ static cplx filter_run(cplx a1, cplx b0, int32_t d, const double* xr, const doub
         acc[k] += y;
     }
     return y;
+}
+
+/* Threads of the template loop (n <= 0: the OpenMP default); returns the count
+ * the next parallel region will use.  Timing only: results do not depend on it. */
+int oracle_threads(int n)
+{
+    static int dflt = 0;
+    if (dflt == 0) dflt = omp_get_max_threads();
+    omp_set_num_threads(n > 0 ? n : dflt);
+    return omp_get_max_threads();
 }
 
 /* Exposed for the closed-form pins: one filter from zero state over a complex
