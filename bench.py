@@ -193,7 +193,7 @@ def serving_bench(args, S, W, torch, np):
     xs_sat = [W.noise_stream(2000 + s, blk * (K + Wm)) for s in range(n_streams)]
     xt = [torch.from_numpy(x.astype(np.float32)).cuda() for x in xs_sat]
     stream = torch.cuda.Stream()
-    bk = [S.Bank(b, max_block, stream=stream) for b in banks]
+    bk = [S.Bank(b, max_block, stream=stream, precision=args.precision) for b in banks]
     zs = [torch.empty((b.n_templates, blk), dtype=torch.complex64, device="cuda") for b in banks]
     fs_step = sum(b.filter_samples_per_block(blk) for b in banks)
     flops = sum(W.algorithmic_flops(b, blk)["filter"] for b in banks)
@@ -228,7 +228,7 @@ def serving_bench(args, S, W, torch, np):
     def serve(policy, speed, seconds):
         arr = W.serving_arrivals(5005, n_streams, seconds, rate_hz=rate, speed=speed)
         xs = [W.noise_stream(2100 + s, int(l.sum())) for s, (l, _) in enumerate(arr)]
-        be = SV.HipBackend(xs, n_streams=2)
+        be = SV.HipBackend(xs, n_streams=2, precision=args.precision)
         sch = SV.Scheduler(be, banks, max_block=max_block, policy=policy)
         blocks = SV.make_arrivals(arr)
         st = sch.run(blocks)
@@ -269,7 +269,8 @@ def serving_bench(args, S, W, torch, np):
                    "streams": n_streams, "bands": 7, "base_rate_hz": rate,
                    "saturated_step": "one 1 s block of every stream per batch",
                    "filters_per_lane": plan["filters_per_lane"],
-                   "lanes_per_group": plan["lanes_per_group"], "carry_chunk": plan["carry_chunk"]},
+                   "lanes_per_group": plan["lanes_per_group"], "carry_chunk": plan["carry_chunk"],
+                   "precision": args.precision},
         "real_time_templates": total_t * cap["batched"],
         "real_time_templates_plain": total_t * cap["plain"],
         "block_latency_ms": {"p50": rt["batched"].get("p50_ms"), "p99": rt["batched"].get("p99_ms"),
@@ -306,7 +307,9 @@ def main():
     ap.add_argument("--carry-chunk", type=int, default=0)
     ap.add_argument("--time-chunks", type=int, default=0,
                     help="split every block in time into this many chunks (small banks)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_compensated"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp32_compensated"],
+                    help="summation over filters (default: compensated for the multi-rate "
+                         "configurations 3 and 5, which name it, plain FP32 otherwise)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate lane packings first and use the fastest")
     ap.add_argument("--tune-block", action="store_true",
@@ -334,6 +337,8 @@ def main():
     from paper_1702_02256_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.precision is None:
+        args.precision = "fp32_compensated" if args.config in (3, 5) else "fp32"
     if args.config == 5:
         return serving_bench(args, S, W, torch, np)
     K, Wm = args.steps, args.warmup

@@ -383,22 +383,30 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F)) k_
                     for (int i = 0; i < kPairs; ++i) v[i] = grp[i * (kTile + 1)];
                     c32* out = l2 + j1 * nrun;
                     if (endmask == (1u << (kPairs - 1))) {
-                        // the whole group is one run
-                        float accr = v[0].x, acci = v[0].y, er = 0.0f, ei = 0.0f;
+                        // the whole group is one run: a pairwise tree (short dependency
+                        // chains), error-free additions when compensated
+                        float tr[kPairs], ti[kPairs], er = 0.0f, ei = 0.0f;
     #pragma unroll
-                        for (int i = 1; i < kPairs; ++i) {
-                            if (COMP) {
-                                float e1, e2;
-                                two_sum(accr, v[i].x, accr, e1);
-                                two_sum(acci, v[i].y, acci, e2);
-                                er += e1;
-                                ei += e2;
-                            } else {
-                                accr += v[i].x;
-                                acci += v[i].y;
-                            }
+                        for (int i = 0; i < kPairs; ++i) {
+                            tr[i] = v[i].x;
+                            ti[i] = v[i].y;
                         }
-                        out[slot0] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
+    #pragma unroll
+                        for (int st = 1; st < kPairs; st *= 2)
+    #pragma unroll
+                            for (int i = 0; i + st < kPairs; i += 2 * st) {
+                                if (COMP) {
+                                    float e1, e2;
+                                    two_sum(tr[i], tr[i + st], tr[i], e1);
+                                    two_sum(ti[i], ti[i + st], ti[i], e2);
+                                    er += e1;
+                                    ei += e2;
+                                } else {
+                                    tr[i] += tr[i + st];
+                                    ti[i] += ti[i + st];
+                                }
+                            }
+                        out[slot0] = (COMP ? c32{tr[0] + er, ti[0] + ei} : c32{tr[0], ti[0]});
                     } else {
                         int slot = slot0;
                         float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
