@@ -217,7 +217,7 @@ __device__ __forceinline__ Chunk chunk_range(int c, int nchunk, int64_t s0h, int
 // no output).  Otherwise: the filter pass proper, each chunk starting from its
 // chained state.
 template <int F, bool COMP, bool LOCAL>
-__global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F)) k_filter(LaunchArgs args)
+__global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COMP)) k_filter(LaunchArgs args)
 {
     extern __shared__ float sm[];
     const int bid = blockIdx.x;
@@ -308,6 +308,10 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F)) k_
             if (slot0 < 0) slot0 = sl;
         }
     }
+    // The single-run form applies when every 16-lane group the wave reduces is
+    // one run; otherwise the whole wave takes the segmented form (which also
+    // handles single-run groups), so no wave executes both.
+    const bool wave_single_run = __all(endmask == (1u << (kRunLanes / 2 - 1)));
 
     const int S = bd->S[h];
     const float* ring = bd->rings + bd->ring_off[h];
@@ -382,7 +386,7 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F)) k_
     #pragma unroll
                     for (int i = 0; i < kPairs; ++i) v[i] = grp[i * (kTile + 1)];
                     c32* out = l2 + j1 * nrun;
-                    if (endmask == (1u << (kPairs - 1))) {
+                    if (wave_single_run) {
                         // the whole group is one run: a pairwise tree (short dependency
                         // chains), error-free additions when compensated
                         float tr[kPairs], ti[kPairs], er = 0.0f, ei = 0.0f;
@@ -408,28 +412,26 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F)) k_
                             }
                         out[slot0] = (COMP ? c32{tr[0] + er, ti[0] + ei} : c32{tr[0], ti[0]});
                     } else {
+                        // runs in order; the accumulator restarts after a run end by a
+                        // multiplication with keep = 0 (exact, and no selects)
                         int slot = slot0;
-                        float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
-                        bool fresh = true;
+                        float accr = v[0].x, acci = v[0].y, er = 0.0f, ei = 0.0f;
     #pragma unroll
                         for (int i = 0; i < kPairs; ++i) {
-                            if (fresh) {
-                                accr = v[i].x;
-                                acci = v[i].y;
-                                er = 0.0f;
-                                ei = 0.0f;
-                            } else if (COMP) {
-                                float e1, e2;
-                                two_sum(accr, v[i].x, accr, e1);
-                                two_sum(acci, v[i].y, acci, e2);
-                                er += e1;
-                                ei += e2;
-                            } else {
-                                accr += v[i].x;
-                                acci += v[i].y;
+                            if (i > 0) {
+                                const float keep = (float)(((endmask >> (i - 1)) & 1u) ^ 1u);
+                                if (COMP) {
+                                    float e1, e2;
+                                    two_sum(accr * keep, v[i].x, accr, e1);
+                                    two_sum(acci * keep, v[i].y, acci, e2);
+                                    er = fmaf(er, keep, e1);
+                                    ei = fmaf(ei, keep, e2);
+                                } else {
+                                    accr = fmaf(accr, keep, v[i].x);
+                                    acci = fmaf(acci, keep, v[i].y);
+                                }
                             }
-                            fresh = (endmask >> i) & 1u;
-                            if (fresh) {
+                            if ((endmask >> i) & 1u) {
                                 out[slot] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
                                 ++slot;
                             }
