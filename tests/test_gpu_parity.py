@@ -130,8 +130,8 @@ def test_config3_full_size_sampled():
     nb = 16
     wl = W.config3(n_blocks=nb)
     x = wl.stream()
-    _say("cfg3 full: 4096 templates x 7 bands, 16 blocks of 4096, sampled check")
-    bank = S.Bank(wl.bank, 4096)
+    _say("cfg3 full: 4096 templates x 7 bands, 16 blocks of 4096, compensated, sampled check")
+    bank = S.Bank(wl.bank, 4096, precision="fp32_compensated")  # the benchmark's form
     xt = torch.from_numpy(x.astype(np.float32)).cuda()
     sel = np.sort(np.random.default_rng(98).choice(4096, 6, replace=False))
     selt = torch.as_tensor(sel, device="cuda")
@@ -143,6 +143,53 @@ def test_config3_full_size_sampled():
     zg = np.concatenate(parts, axis=1)
     zr = oracle.run_stream(wl.bank.subset(sel), x)
     check(zg, zr, label="cfg3-full-sampled")
+    bank.destroy()
+
+
+def test_config4_full_size_sampled():
+    """All 8192 uneven templates in 2048-sample blocks (the tuned block length)."""
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    wl = W.config4(n_blocks=2)
+    x = wl.stream()[: 4 * 2048]
+    _say("cfg4 full: 8192 uneven templates, 4 blocks of 2048, sampled check")
+    bank = S.Bank(wl.bank, 2048)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    sel = np.sort(np.random.default_rng(97).choice(8192, 8, replace=False))
+    selt = torch.as_tensor(sel, device="cuda")
+    z = torch.zeros((8192, 2048), dtype=torch.complex64, device="cuda")
+    parts = []
+    for i in range(4):
+        bank.process_block(xt[i * 2048:(i + 1) * 2048], z)
+        parts.append(z[selt].cpu().numpy().astype(np.complex128))
+    zg = np.concatenate(parts, axis=1)
+    zr = oracle.run_stream(wl.bank.subset(sel), x)
+    check(zg, zr, label="cfg4-full-sampled")
+    bank.destroy()
+
+
+def test_serving_bank_full_size_sampled():
+    """One serving bank (5462 multi-rate templates) as the serving benchmark
+    runs it: compensated, 8192-sample max block, uneven blocks."""
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    tb = W.serving_banks()[0]
+    blocks = [4096, 512, 8192, 1536]
+    x = W.noise_stream(2000, sum(blocks))
+    _say(f"cfg5 bank full: {tb.n_templates} templates, blocks {blocks}, sampled check")
+    bank = S.Bank(tb, 8192, precision="fp32_compensated")
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    sel = np.sort(np.random.default_rng(96).choice(tb.n_templates, 6, replace=False))
+    selt = torch.as_tensor(sel, device="cuda")
+    parts, pos = [], 0
+    for n in blocks:
+        z = torch.zeros((tb.n_templates, n), dtype=torch.complex64, device="cuda")
+        bank.process_block(xt[pos:pos + n], z)
+        parts.append(z[selt].cpu().numpy().astype(np.complex128))
+        pos += n
+    zg = np.concatenate(parts, axis=1)
+    zr = oracle.run_stream(tb.subset(sel), x)
+    check(zg, zr, label="cfg5-bank-full-sampled")
     bank.destroy()
 
 
