@@ -23,7 +23,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
 METRIC = "template-filter-samples/s + real-time templates/GPU; p99 block latency"
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("paper_1702_02256_amd/csrc/spiir_kernels.hip", "paper_1702_02256_amd/csrc/spiir_internal.h")
+KERNEL_SOURCES = ("paper_1702_02256_amd/csrc/spiir_kernels.hip", "paper_1702_02256_amd/csrc/spiir_internal.h",
+                  "paper_1702_02256_amd/csrc/spiir_host.cpp")
 
 
 def kernel_source_hash() -> str:

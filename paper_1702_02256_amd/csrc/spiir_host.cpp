@@ -20,7 +20,8 @@ namespace {
 constexpr int kDefaultF = 4;
 constexpr int kDefaultW = 8;
 constexpr int kDefaultC = 32;
-constexpr int kSubBlock = 512;      // samples per LDS window restage
+constexpr int kSubBlock = 1024;     // samples per LDS window restage (largest tried)
+constexpr int kNoFit = 1;           // internal: this launch shape exceeds the LDS budget
 constexpr int kXcapMax = 24576;     // LDS window, floats
 constexpr int kMaxLds = 160 * 1024;
 constexpr uint32_t kStateMagic = 0x53504952u;  // "SPIR"
@@ -104,15 +105,13 @@ int validate(const spiir_bank_desc* d)
 // workgroups of L lanes; a segment crossing a workgroup boundary becomes two
 // pieces.  Padding lanes and slots carry zero coefficients (their outputs are
 // exactly zero) and belong to the last piece of their workgroup.
-int make_plan(const spiir_bank_desc* d, Plan& p)
+int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
 {
-    int rc = validate(d);
-    if (rc) return rc;
     p = Plan();
     p.T = d->n_templates;
     p.H = d->n_bands;
     p.F = d->filters_per_lane ? d->filters_per_lane : kDefaultF;
-    p.W = d->waves_per_group ? d->waves_per_group : kDefaultW;
+    p.W = W;
     p.L = 64 * p.W;
     p.C = d->carry_chunk ? d->carry_chunk : kDefaultC;
     p.precision = d->precision;
@@ -146,13 +145,13 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
                 p.maxd_band[h] = std::max(p.maxd_band[h], (int)d->delay[moff[t * H + h] + l]);
 
     // LDS window: two copies (x and x shifted by one sample) of up to
-    // maxd + S + 64 samples each, S = min(block, kSubBlock); a copy's size is
+    // maxd + S + 64 samples each, S = min(block, sub); a copy's size is
     // 32 mod 64 dwords so that the second copy starts 32 banks after the first.
     int X = 0;
     for (int h = 0; h < H; ++h)
-        X = std::max(X, p.maxd_band[h] + std::min(kSubBlock, p.mb_inner >> h) + 65);
+        X = std::max(X, p.maxd_band[h] + std::min(sub, p.mb_inner >> h) + 65);
     X = ((X + 63) & ~63) + 32;
-    if (X > kXcapMax) return SPIIR_EINVAL;
+    if (X > kXcapMax) return kNoFit;
     p.xcap = X;
     p.S.assign(H, 0);
     p.zstride.assign(H, 0);
@@ -161,7 +160,7 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
     p.ring_off.assign(H, 0);
     for (int h = 0; h < H; ++h) {
         const int nh = p.mb_inner >> h;
-        p.S[h] = std::min(kSubBlock, nh);
+        p.S[h] = std::min(sub, nh);
         const int64_t P = next_pow2((int64_t)nh + std::max(p.maxd_band[h], p.td) + 1);
         p.ring_mask[h] = (int)(P - 1);
         p.ring_off[h] = p.ring_total;
@@ -349,7 +348,8 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
                    L * 4 + p.npiece_max * 8;
     p.lds_stage = ((p.td - 1) + p.mb_inner + (p.td - 1) + p.mb_inner / 2 + p.td) * 4;
     p.lds_up = (2 * (p.hu_len + p.mb_inner / 2) + std::max(p.H - 2, 0) * p.hu_len) * 8 + p.tu * 4;
-    if (p.lds_filter > kMaxLds || p.lds_stage > kMaxLds || p.lds_up > kMaxLds) return SPIIR_EINVAL;
+    if (p.lds_stage > kMaxLds || p.lds_up > kMaxLds) return SPIIR_EINVAL;
+    if (p.lds_filter > kMaxLds) return kNoFit;
 
     size_t fp = 0;
     fp += (size_t)p.n_slots * (5 * sizeof(c32) + sizeof(int32_t));
@@ -363,6 +363,28 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
         fp += (size_t)p.n_slots * sizeof(c32) * (1 + 2 * (size_t)(p.P + 1) + 1);
     p.footprint = fp;
     return SPIIR_OK;
+}
+
+// The launch shape: the caller's waves per group, or by default 8 waves and
+// fewer when a bank's delay window does not fit the LDS at 8 (long delays);
+// the window sub-block shrinks first.
+int make_plan(const spiir_bank_desc* d, Plan& p)
+{
+    int rc = validate(d);
+    if (rc) return rc;
+    const int F = d->filters_per_lane ? d->filters_per_lane : kDefaultF;
+    std::vector<int> ws;
+    if (d->waves_per_group)
+        ws.push_back(d->waves_per_group);
+    else
+        for (int w : {kDefaultW, 4, 2, 1})
+            if (64 * w <= filter_max_threads(F)) ws.push_back(w);
+    for (int w : ws)
+        for (int sub : {kSubBlock, 512, 256, 128, 64}) {
+            rc = make_plan_shape(d, p, w, sub);
+            if (rc != kNoFit) return rc;
+        }
+    return SPIIR_EINVAL;
 }
 
 // ---------------------------------------------------------------- profiling

@@ -163,3 +163,17 @@ def test_plan_time_chunks():
     # chunk states and the a1^length table are allocated only for a split bank
     assert p32["footprint"] > p1["footprint"]
     assert S.spiir_plan(wl.bank, 4096, time_chunks=1)["footprint"] == p1["footprint"]
+
+
+def test_long_delays_fall_back_to_a_smaller_launch_shape():
+    # a delay window of 16383 samples does not fit the LDS next to 8-wave reduction
+    # buffers; the default shape steps down instead of refusing the bank
+    tb = W.random_bank(21, np.array([[64], [64]], np.int32), 4096, [16383])
+    tb.delay = tb.delay.copy()
+    tb.delay[0] = 16383
+    p = S.spiir_plan(tb, 4096)
+    assert p["lanes_per_group"] < 512 and p["lds_bytes"] <= 160 * 1024
+    with pytest.raises(S.SpiirError):
+        S.spiir_plan(tb, 4096, waves_per_group=8)  # an explicit shape is not changed
+    # ordinary delays keep the 8-wave default
+    assert S.spiir_plan(W.config3(n_templates=8, n_blocks=1).bank, 4096)["lanes_per_group"] == 512

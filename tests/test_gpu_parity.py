@@ -247,6 +247,17 @@ def test_large_delays_use_subblocks():
     check(zg, zr, label="large-delays")
 
 
+def test_largest_delay_with_the_default_shape():
+    nf = np.array([[64], [64]], np.int32)
+    tb = W.random_bank(21, nf, 4096, [16383])
+    tb.delay = tb.delay.copy()
+    tb.delay[:4] = 16383
+    x = W.noise_stream(22, 6 * 4096)
+    zg = run_gpu(tb, x, [4096] * 6)
+    zr = oracle.run_stream(tb, x)
+    check(zg, zr, label="max-delay")
+
+
 @pytest.mark.parametrize("F,Wv", [(1, 1), (2, 2), (4, 4), (8, 4), (8, 8), (4, 8), (1, 8)])
 def test_lane_packing_variants(F, Wv):
     tb = _mr_bank(seed=15, T=6, H=3, lo=1, hi=300)
