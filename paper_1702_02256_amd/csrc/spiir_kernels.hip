@@ -499,6 +499,10 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
 // LDS: e0 [hu_len + max_block/2] c32 | e1 [same] | taps [tu]
 // ---------------------------------------------------------------------------
 constexpr int kUpThreads = 256;
+constexpr int kUpFastTaps = 32;  // interpolator length with an unrolled path
+// read-only device memory in the constant address space: uniform loads of it
+// become scalar loads that the compiler may repeat instead of holding registers
+typedef const __attribute__((address_space(4))) float ConstF;
 
 // low-rate samples per thread for the boundary between band h and h+1
 __host__ __device__ constexpr int up_slots(int h)
@@ -509,7 +513,9 @@ __host__ __device__ constexpr int up_slot_base(int h)
 {
     return h == 0 ? 0 : up_slot_base(h - 1) + up_slots(h - 1);
 }
-constexpr int kUpSlotsTotal = up_slot_base(kMaxBands - 1);
+constexpr int kUpSlotsTotal = up_slot_base(kMaxBands);
+// sample pairs (2m, 2m+1) of band h in a block of n base-rate samples
+__device__ __forceinline__ int up_pairs(int n, int h) { return ((n >> h) + 1) >> 1; }
 
 __device__ __forceinline__ c32 piece_sum(const c32* zw, const SegDesc& sg, int64_t stride, int k)
 {
@@ -584,7 +590,7 @@ __device__ void peak_store(PeakAcc a, const ReqArg& q, int t, int tid, float* ld
     *pk = spiir_peak{v, idx, cnt, 0};
 }
 
-__global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
+__global__ void __launch_bounds__(kUpThreads, 4) k_upadd(LaunchArgs args)
 {
     extern __shared__ float sm[];
     const int bid = blockIdx.x;
@@ -599,6 +605,12 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
     c32* zrow = q.z ? q.z + (int64_t)t * q.ldz : nullptr;
     const bool peaks = q.peaks != nullptr;
     PeakAcc acc;
+    // The common 32-tap interpolator runs with its taps in registers (read
+    // before any store, so as uniform scalar loads) and the tap loop unrolled;
+    // other lengths read the taps from LDS.  Both add the terms in the same
+    // order, so they give the same bits.
+    const bool taps32 = tu == kUpFastTaps;
+    const ConstF* tap = (const ConstF*)(bd->hu);
 
     if (H == 1) {
         const SegDesc sg = seg[0];
@@ -620,30 +632,32 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
     const c32* hist_in = bd->uphist + ((int64_t)t * H + 1) * HU;
     for (int i = tid; i < (H - 2) * HU; i += kUpThreads) hl[i] = hist_in[i];
 
-    // every other band's own output, both phases per low-rate sample.  The
-    // first piece of every band is loaded for all slots at once (independent
-    // loads, one wait), then the other pieces of split segments are added.
+    // every band's own output, as sample pairs (2m, 2m+1) (the lowest band may
+    // end on an unpaired sample; its partner is a workspace word that is read
+    // but not used).  The first piece of
+    // every band is loaded for all slots at once (independent loads, one
+    // wait), then the other pieces of split segments are added.
     float4 pv[kUpSlotsTotal];
 #pragma unroll
-    for (int h = 0; h < kMaxBands - 1; ++h) {
+    for (int h = 0; h < kMaxBands; ++h) {
 #pragma unroll
         for (int i = 0; i < up_slots(h); ++i) {
             pv[up_slot_base(h) + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             const int m = tid + kUpThreads * i;
-            if (h < H - 1 && m < (n >> (h + 1)) && seg[h].npiece > 0)
+            if (h < H && m < up_pairs(n, h) && seg[h].npiece > 0)
                 pv[up_slot_base(h) + i] =
                     *reinterpret_cast<const float4*>(bd->zw + seg[h].zoff + 2 * m);
         }
     }
 #pragma unroll
-    for (int h = 0; h < kMaxBands - 1; ++h) {
-        if (h >= H - 1) continue;
+    for (int h = 0; h < kMaxBands; ++h) {
+        if (h >= H) continue;
         const SegDesc sg = seg[h];
         for (int p = 1; p < sg.npiece; ++p) {
 #pragma unroll
             for (int i = 0; i < up_slots(h); ++i) {
                 const int m = tid + kUpThreads * i;
-                if (m < (n >> (h + 1))) {
+                if (m < up_pairs(n, h)) {
                     const float4 u =
                         *reinterpret_cast<const float4*>(bd->zw + sg.zoff + p * bd->zstride[h] + 2 * m);
                     float4& v = pv[up_slot_base(h) + i];
@@ -658,11 +672,23 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
 
     // lowest band: acc_{H-1} = z_{H-1}, placed after its history
     {
-        const int h = H - 1, nh = n >> h;
-        const SegDesc sg = seg[h];
-        c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
+        const int nh = n >> (H - 1);
+        c32* hist = bd->uphist + ((int64_t)t * H + H - 1) * HU;
         for (int i = tid; i < HU; i += kUpThreads) cur[i] = hist[i];
-        for (int k = tid; k < nh; k += kUpThreads) cur[HU + k] = piece_sum(bd->zw, sg, bd->zstride[h], k);
+#pragma unroll
+        for (int h = 1; h < kMaxBands; ++h) {
+            if (h == H - 1) {
+#pragma unroll
+                for (int i = 0; i < up_slots(h); ++i) {
+                    const int m = tid + kUpThreads * i;
+                    if (m < up_pairs(n, h)) {
+                        const float4 v = pv[up_slot_base(h) + i];
+                        cur[HU + 2 * m] = c32{v.x, v.y};
+                        if (2 * m + 1 < nh) cur[HU + 2 * m + 1] = c32{v.z, v.w};
+                    }
+                }
+            }
+        }
         __syncthreads();
         for (int i = tid; i < HU; i += kUpThreads) hist[i] = cur[nh + i];
     }
@@ -675,22 +701,38 @@ __global__ void __launch_bounds__(kUpThreads) k_upadd(LaunchArgs args)
             c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
             if (h > 0)
                 for (int i = tid; i < HU; i += kUpThreads) nxt[i] = hl[(h - 1) * HU + i];
+            // all of the thread's slots hold samples of this block
+            const bool full = nlo >= kUpThreads * up_slots(h);
 #pragma unroll
             for (int i = 0; i < up_slots(h); ++i) {
                 const int m = tid + kUpThreads * i;
-                if (m < nlo) {
+                if (full || m < nlo) {
                     const float4 v = pv[up_slot_base(h) + i];
                     float er = v.x, ei = v.y, orr = v.z, oi = v.w;
                     const c32* a = cur + HU + m;
-                    for (int j = 0; j < ne; ++j) {
-                        const c32 u = a[-j];
-                        const float ce = hu[2 * j];
-                        er = fmaf(ce, u.x, er);
-                        ei = fmaf(ce, u.y, ei);
-                        if (j < no) {
-                            const float co = hu[2 * j + 1];
-                            orr = fmaf(co, u.x, orr);
-                            oi = fmaf(co, u.y, oi);
+                    if (taps32) {
+                        // the whole window first (independent LDS reads), then the taps
+                        c32 u[kUpFastTaps / 2];
+#pragma unroll
+                        for (int j = 0; j < kUpFastTaps / 2; ++j) u[j] = a[-j];
+#pragma unroll
+                        for (int j = 0; j < kUpFastTaps / 2; ++j) {
+                            er = fmaf(tap[2 * j], u[j].x, er);
+                            ei = fmaf(tap[2 * j], u[j].y, ei);
+                            orr = fmaf(tap[2 * j + 1], u[j].x, orr);
+                            oi = fmaf(tap[2 * j + 1], u[j].y, oi);
+                        }
+                    } else {
+                        for (int j = 0; j < ne; ++j) {
+                            const c32 u = a[-j];
+                            const float ce = hu[2 * j];
+                            er = fmaf(ce, u.x, er);
+                            ei = fmaf(ce, u.y, ei);
+                            if (j < no) {
+                                const float co = hu[2 * j + 1];
+                                orr = fmaf(co, u.x, orr);
+                                oi = fmaf(co, u.y, oi);
+                            }
                         }
                     }
                     if (h == 0) {

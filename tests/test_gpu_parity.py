@@ -238,6 +238,17 @@ def test_edge_shapes():
     assert np.any(zg[3] != 0) and np.any(zg[1] != 0)
 
 
+@pytest.mark.parametrize("n_down,n_up", [(17, 15), (48, 24), (32, 2), (20, 33)])
+def test_other_resampler_lengths(n_down, n_up):
+    """Interpolators other than the common 32 taps take the generic up-add path."""
+    nf = np.random.default_rng(15).integers(1, 70, size=(4, 4)).astype(np.int32)
+    tb = W.random_bank(15, nf, 1024, W.multirate_dmax(1024, 4), n_taps_down=n_down, n_taps_up=n_up)
+    x = W.noise_stream(16, 3 * 1024)
+    zg = run_gpu(tb, x, [1024, 512, 8, 1528], max_block=2048)
+    zr = oracle.run_stream(tb, x)
+    check(zg, zr, label=f"taps {n_down}/{n_up}")
+
+
 def test_large_delays_use_subblocks():
     nf = np.array([[64], [64]], np.int32)
     tb = W.random_bank(13, nf, 4096, [12000])
