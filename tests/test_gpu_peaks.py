@@ -37,12 +37,12 @@ def _check_exact(got, z, thr, label):
     assert np.array_equal(got["n_above"], cnt), label
 
 
-def _run(tables, x, blocks, thr, write_z=True, max_block=None):
+def _run(tables, x, blocks, thr, write_z=True, max_block=None, **kw):
     import torch
     from paper_1702_02256_amd import spiir as S
     T = tables.n_templates
-    bank = S.Bank(tables, max_block or max(blocks))
-    plain = S.Bank(tables, max_block or max(blocks))
+    bank = S.Bank(tables, max_block or max(blocks), **kw)
+    plain = S.Bank(tables, max_block or max(blocks), **kw)
     xt = torch.from_numpy(np.asarray(x, np.float32)).cuda()
     pk = S.peaks_empty(T)
     out = []
@@ -106,6 +106,25 @@ def test_peaks_without_z_and_long_blocks():
             assert np.array_equal(ga[k].view(np.uint32), gb[k].view(np.uint32)), k
     # the peak of at least one template falls in the second launch chunk
     assert any((g["index"] >= 4096).any() for g, _ in with_z)
+
+
+def test_peaks_with_a_time_split():
+    """The reduction runs once per block after the chunked filter passes."""
+    nf = np.array([[90], [7], [130]], np.int32)
+    tb = W.random_bank(17, nf, 4096, [1500])
+    x = W.noise_stream(18, 3 * 4096)
+    thr = 1e-3
+    blocks = [4096, 1000, 3096, 4096]
+    _say("peaks with time_chunks=8: 3 templates, blocks 4096, 1000, 3096, 4096")
+    res = _run(tb, x, blocks, thr, time_chunks=8, filters_per_lane=1, waves_per_group=2)
+    zr = oracle.run_stream(tb, x)
+    pos = 0
+    for i, ((got, zg), n) in enumerate(zip(res, blocks)):
+        _check_exact(got, zg, thr, f"split block {i}")
+        top = np.abs(zr[:, pos:pos + n]).max(axis=1)
+        scale = np.abs(zr).max(axis=1)
+        assert np.all(np.abs(np.sqrt(got["peak2"].astype(np.float64)) - top) <= TOL * scale)
+        pos += n
 
 
 def test_peaks_single_rate_batch_and_ties():
