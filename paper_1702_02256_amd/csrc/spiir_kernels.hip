@@ -25,6 +25,33 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
     e = (a - (s - bp)) + (b - bp);
 }
 
+// Address-space views of device memory.  Pointers held in the bank
+// descriptor are generic; through a generic pointer the compiler emits flat
+// accesses, which count against the LDS wait counter too, so a wait for an
+// LDS read would also wait for every outstanding flat store or load.  Memory
+// that no thread writes during a kernel (the descriptor, coefficient tables,
+// input rings, the clock) is read through the constant view, which also lets
+// uniform reads become scalar loads; memory a kernel writes, or reads and
+// writes, goes through the global view.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SPIIR_AS_GLOBAL __attribute__((address_space(1)))
+#define SPIIR_AS_CONST __attribute__((address_space(4)))
+#else  // the host pass over this file only parses the kernels
+#define SPIIR_AS_GLOBAL
+#define SPIIR_AS_CONST
+#endif
+template <class T>
+__device__ __forceinline__ SPIIR_AS_GLOBAL T* gmem(T* p)
+{
+    return (SPIIR_AS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const SPIIR_AS_CONST T* cmem(const T* p)
+{
+    return (const SPIIR_AS_CONST T*)p;
+}
+typedef const SPIIR_AS_CONST BankDev CBankDev;
+
 // ---------------------------------------------------------------------------
 // Input staging and the downsample cascade (one workgroup per request).
 constexpr int kStageThreads = 1024;
@@ -35,19 +62,22 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
     extern __shared__ float sm[];
     __shared__ long long s_base;
     const ReqArg& q = args.req[blockIdx.x];
-    const BankDev* bd = q.bd;
+    CBankDev* bd = cmem(q.bd);
+    SPIIR_AS_GLOBAL int64_t* clock = gmem(bd->clock);
+    const SPIIR_AS_GLOBAL float* x = gmem(q.x);
     const int n = q.n;
-    if (threadIdx.x == 0) s_base = bd->clock[1];
+    if (threadIdx.x == 0) s_base = clock[1];
     __syncthreads();
     const int64_t s0 = s_base;
     if (threadIdx.x == 0) {
-        bd->clock[0] = s0;      // read by the filter kernel that follows
-        bd->clock[1] = s0 + n;
+        clock[0] = s0;      // read by the filter kernel that follows
+        clock[1] = s0 + n;
     }
     const int H = bd->H;
-    float* ring0 = bd->rings + bd->ring_off[0];
+    SPIIR_AS_GLOBAL float* rings = gmem(bd->rings);
+    SPIIR_AS_GLOBAL float* ring0 = rings + bd->ring_off[0];
     const int64_t m0 = bd->ring_mask[0];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) ring0[(s0 + i) & m0] = q.x[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ring0[(s0 + i) & m0] = x[i];
     if (H == 1) return;
 
     const int td = bd->td;
@@ -55,15 +85,15 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
     float* cur = sm;
     float* nxt = sm + hl + bd->max_block;
     float* hd = nxt + hl + bd->max_block / 2;
-    for (int i = threadIdx.x; i < td; i += blockDim.x) hd[i] = bd->hd[i];
+    for (int i = threadIdx.x; i < td; i += blockDim.x) hd[i] = cmem(bd->hd)[i];
     for (int i = threadIdx.x; i < hl; i += blockDim.x) cur[i] = ring0[(s0 - hl + i) & m0];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) cur[hl + i] = q.x[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) cur[hl + i] = x[i];
     __syncthreads();
 
     for (int h = 1; h < H; ++h) {
         const int nh = n >> h;
         const int64_t s0h = s0 >> h;
-        float* ring = bd->rings + bd->ring_off[h];
+        SPIIR_AS_GLOBAL float* ring = rings + bd->ring_off[h];
         const int64_t mk = bd->ring_mask[h];
         if (h < H - 1)
             for (int i = threadIdx.x; i < hl; i += blockDim.x) nxt[i] = ring[(s0h - hl + i) & mk];
@@ -212,6 +242,8 @@ __device__ __forceinline__ Chunk chunk_range(int c, int nchunk, int64_t s0h, int
     return r;
 }
 
+constexpr int kStageBatch = 4;  // window loads a thread keeps in flight
+
 // LOCAL: the end-state pass of a time split (every chunk but the last runs
 // from zero, or the first from the carried state, and stores its end state;
 // no output).  Otherwise: the filter pass proper, each chunk starting from its
@@ -229,15 +261,15 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
     }
     const ReqArg& q = args.req[args.seg_req[lo]];
     const int h = args.seg_band[lo];
-    const BankDev* bd = q.bd;
+    CBankDev* bd = cmem(q.bd);
     const int nwg_h = bd->band_wg0[h + 1] - bd->band_wg0[h];
     const int li = bid - args.cum[lo];
     const int tc = li / nwg_h;  // time chunk (chunk-major order)
-    const WgDesc wg = bd->wg[bd->band_wg0[h] + (li - tc * nwg_h)];
+    const WgDesc wg = cmem(bd->wg)[bd->band_wg0[h] + (li - tc * nwg_h)];
     const int L = blockDim.x;
     const int tid = threadIdx.x;
     const int nh = q.n >> h;
-    const int64_t s0h = bd->clock[0] >> h;  // set by the staging kernel of this chunk
+    const int64_t s0h = cmem(bd->clock)[0] >> h;  // set by the staging kernel of this chunk
     const Chunk ch = chunk_range(tc, q.nchunk, s0h, nh, bd->lc[h]);
     if (ch.k0 >= ch.k1 || (LOCAL && ch.last)) return;  // whole workgroup
     const int64_t cmask = bd->C - 1;
@@ -253,9 +285,9 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
     int* lmeta = reinterpret_cast<int*>(pzoff + bd->npiece_max);
     int2* prun = reinterpret_cast<int2*>(lmeta + L);
 
-    lmeta[tid] = bd->lane_meta[wg.meta_base + tid];
+    lmeta[tid] = cmem(bd->lane_meta)[wg.meta_base + tid];
     for (int p = tid; p < wg.npiece; p += L) {
-        const PieceDesc pd = bd->piece[wg.piece_base + p];
+        const PieceDesc pd = cmem(bd->piece)[wg.piece_base + p];
         pzoff[p] = pd.zoff;
         prun[p] = make_int2(pd.run0, pd.run1);
     }
@@ -276,22 +308,24 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
         ysrc = bd->schain + (int64_t)tc * bd->n_slots;
         yssrc = bd->ys0;
     }
+    const SPIIR_AS_GLOBAL c32* ysg = gmem(ysrc);
+    const SPIIR_AS_GLOBAL c32* yssg = gmem(yssrc);
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int64_t g = wg.slot_base + (int64_t)f * L + tid;
-        c32 y = ysrc[g], ys = yssrc[g];
+        c32 y = ysg[g], ys = yssg[g];
         if (LOCAL && !ch.first) y = ys = c32{0.0f, 0.0f};
         if (LOCAL && ch.first) {
-            bd->schain[(int64_t)tc * bd->n_slots + g] = y;
-            bd->ys0[g] = ys;
+            gmem(bd->schain)[(int64_t)tc * bd->n_slots + g] = y;
+            gmem(bd->ys0)[g] = ys;
         }
-        const c32 a = bd->a[g], b = bd->b[g], d = bd->dc[g];
+        const c32 a = cmem(bd->a)[g], b = cmem(bd->b)[g], d = cmem(bd->dc)[g];
         ar[f] = a.x; ai[f] = a.y;
         br[f] = b.x; bi[f] = b.y;
         dr[f] = d.x; di[f] = d.y;
         yr[f] = y.x; yi[f] = y.y;
         sr[f] = ys.x; si[f] = ys.y;
-        dl[f] = bd->off[g];
+        dl[f] = cmem(bd->off)[g];
     }
     __syncthreads();
 
@@ -314,8 +348,9 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
     const bool wave_single_run = __all(endmask == (1u << (kRunLanes / 2 - 1)));
 
     const int S = bd->S[h];
-    const float* ring = bd->rings + bd->ring_off[h];
+    const SPIIR_AS_CONST float* ring = cmem(bd->rings) + bd->ring_off[h];
     const int64_t mk = bd->ring_mask[h];
+    SPIIR_AS_GLOBAL c32* zwg = gmem(bd->zw);
     // Lanes come in pairs of one run (segments span an even number of lanes).
     // The pair sum of sample j is entry e = lane/2 of row j: pbuf[e*(kTile+1) + j],
     // the even lane storing its real part and the odd lane its imaginary part.
@@ -330,10 +365,20 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
         const int64_t origin = ((s0h + kb - wg.maxd - 1) >> 6) << 6;
         const int wn = (int)(s0h + kb + sub - origin);
         __syncthreads();
-        for (int i = tid; i <= wn; i += L) {
-            const float v = ring[(origin + i) & mk];
-            if (i < wn) E0[i] = v;
-            if (i > 0) E1[i - 1] = v;
+        // kStageBatch loads in flight per thread before their LDS stores
+        for (int i0 = tid; i0 <= wn; i0 += kStageBatch * L) {
+            float v[kStageBatch];
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int i = i0 + u * L;
+                v[u] = i <= wn ? ring[(origin + i) & mk] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int i = i0 + u * L;
+                if (i < wn) E0[i] = v[u];
+                if (i > 0 && i <= wn) E1[i - 1] = v[u];
+            }
         }
         __syncthreads();
 
@@ -460,7 +505,7 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
                                 acci += v.y;
                             }
                         }
-                        bd->zw[pzoff[p] + k + j] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
+                        zwg[pzoff[p] + k + j] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
                     }
                 }
             }
@@ -470,7 +515,7 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
     }
 
     if (LOCAL) {
-        c32* ue = bd->uend + (int64_t)tc * bd->n_slots;
+        SPIIR_AS_GLOBAL c32* ue = gmem(bd->uend) + (int64_t)tc * bd->n_slots;
 #pragma unroll
         for (int f = 0; f < F; ++f) ue[wg.slot_base + (int64_t)f * L + tid] = c32{yr[f], yi[f]};
         return;
@@ -480,13 +525,13 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int64_t g = wg.slot_base + (int64_t)f * L + tid;
-        bd->y[g] = c32{yr[f], yi[f]};
-        bd->ys[g] = c32{sr[f], si[f]};
+        gmem(bd->y)[g] = c32{yr[f], yi[f]};
+        gmem(bd->ys)[g] = c32{sr[f], si[f]};
         bad |= !(isfinite(yr[f]) && isfinite(yi[f]));
     }
     if (bad) {
         const int p = lmeta[tid] >> 16;
-        atomicOr(&bd->flags[bd->piece[wg.piece_base + p].tmpl], 1);
+        atomicOr(&bd->flags[cmem(bd->piece)[wg.piece_base + p].tmpl], 1);
     }
 }
 
@@ -500,9 +545,6 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
 // ---------------------------------------------------------------------------
 constexpr int kUpThreads = 256;
 constexpr int kUpFastTaps = 32;  // interpolator length with an unrolled path
-// read-only device memory in the constant address space: uniform loads of it
-// become scalar loads that the compiler may repeat instead of holding registers
-typedef const __attribute__((address_space(4))) float ConstF;
 
 // low-rate samples per thread for the boundary between band h and h+1
 __host__ __device__ constexpr int up_slots(int h)
@@ -517,7 +559,33 @@ constexpr int kUpSlotsTotal = up_slot_base(kMaxBands);
 // sample pairs (2m, 2m+1) of band h in a block of n base-rate samples
 __device__ __forceinline__ int up_pairs(int n, int h) { return ((n >> h) + 1) >> 1; }
 
-__device__ __forceinline__ c32 piece_sum(const c32* zw, const SegDesc& sg, int64_t stride, int k)
+// Adds piece p of band h's segment to the thread's slots of pv (piece 0 is
+// loaded into the zeroed slots, the others are added in piece order).
+__device__ __forceinline__ void up_load(float4 (&pv)[kUpSlotsTotal], int h, const SPIIR_AS_CONST c32* zw,
+                                        const SegDesc& sg, int64_t zstride, int n, int tid, int p)
+{
+    if (sg.npiece <= p) return;
+    const SPIIR_AS_CONST float4* row =
+        reinterpret_cast<const SPIIR_AS_CONST float4*>(zw + sg.zoff + p * zstride);
+#pragma unroll
+    for (int i = 0; i < up_slots(h); ++i) {
+        const int m = tid + kUpThreads * i;
+        if (m < up_pairs(n, h)) {
+            const float4 u = row[m];
+            float4& v = pv[up_slot_base(h) + i];
+            if (p == 0) {
+                v = u;
+            } else {
+                v.x += u.x;
+                v.y += u.y;
+                v.z += u.z;
+                v.w += u.w;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ c32 piece_sum(const SPIIR_AS_CONST c32* zw, const SegDesc& sg, int64_t stride, int k)
 {
     float vr = 0.0f, vi = 0.0f;
     for (int p = 0; p < sg.npiece; ++p) {
@@ -575,7 +643,7 @@ __device__ void peak_store(PeakAcc a, const ReqArg& q, int t, int tid, float* ld
     __syncthreads();
     if (tid != 0) return;
     for (int w = 1; w < kUpThreads / 64; ++w) a.merge(sv[w], si[w], sc[w]);
-    spiir_peak* pk = q.peaks + t;
+    SPIIR_AS_GLOBAL spiir_peak* pk = gmem(q.peaks) + t;
     float v = a.v;
     int idx = a.i == INT_MAX ? -1 : q.c0 + a.i;
     int cnt = a.cnt;
@@ -597,12 +665,13 @@ __global__ void __launch_bounds__(kUpThreads, 4) k_upadd(LaunchArgs args)
     int r = 0;
     while (r + 1 < args.nreq && args.tcum[r + 1] <= bid) ++r;
     const ReqArg& q = args.req[r];
-    const BankDev* bd = q.bd;
+    CBankDev* bd = cmem(q.bd);
     const int t = bid - args.tcum[r];
     const int tid = threadIdx.x;
     const int H = bd->H, n = q.n, HU = bd->hu_len, tu = bd->tu, MB = bd->max_block;
-    const SegDesc* seg = bd->seg + (int64_t)t * H;
-    c32* zrow = q.z ? q.z + (int64_t)t * q.ldz : nullptr;
+    const SPIIR_AS_CONST SegDesc* seg = cmem(bd->seg) + (int64_t)t * H;
+    const SPIIR_AS_CONST c32* zw = cmem(bd->zw);
+    SPIIR_AS_GLOBAL c32* zrow = q.z ? gmem(q.z) + (int64_t)t * q.ldz : nullptr;
     const bool peaks = q.peaks != nullptr;
     PeakAcc acc;
     // The common 32-tap interpolator runs with its taps in registers (read
@@ -610,12 +679,12 @@ __global__ void __launch_bounds__(kUpThreads, 4) k_upadd(LaunchArgs args)
     // other lengths read the taps from LDS.  Both add the terms in the same
     // order, so they give the same bits.
     const bool taps32 = tu == kUpFastTaps;
-    const ConstF* tap = (const ConstF*)(bd->hu);
+    const SPIIR_AS_CONST float* tap = cmem(bd->hu);
 
     if (H == 1) {
         const SegDesc sg = seg[0];
         for (int k = tid; k < n; k += kUpThreads) {
-            const c32 v = piece_sum(bd->zw, sg, bd->zstride[0], k);
+            const c32 v = piece_sum(zw, sg, bd->zstride[0], k);
             if (zrow) zrow[k] = v;
             if (peaks) acc.add(v.x, v.y, k, q.thr2);
         }
@@ -628,52 +697,35 @@ __global__ void __launch_bounds__(kUpThreads, 4) k_upadd(LaunchArgs args)
     c32* nxt = cur + ext;
     c32* hl = nxt + ext;  // histories of bands 1..H-2, loaded once up front
     float* hu = reinterpret_cast<float*>(hl + (H - 2) * HU);
-    for (int i = tid; i < tu; i += kUpThreads) hu[i] = bd->hu[i];
-    const c32* hist_in = bd->uphist + ((int64_t)t * H + 1) * HU;
+    for (int i = tid; i < tu; i += kUpThreads) hu[i] = tap[i];
+    const SPIIR_AS_GLOBAL c32* hist_in = gmem(bd->uphist) + ((int64_t)t * H + 1) * HU;
     for (int i = tid; i < (H - 2) * HU; i += kUpThreads) hl[i] = hist_in[i];
 
-    // every band's own output, as sample pairs (2m, 2m+1) (the lowest band may
+    // Every band's own output, as sample pairs (2m, 2m+1) (the lowest band may
     // end on an unpaired sample; its partner is a workspace word that is read
-    // but not used).  The first piece of
-    // every band is loaded for all slots at once (independent loads, one
-    // wait), then the other pieces of split segments are added.
+    // but not used).  Bands 1.. are loaded for all slots at once (independent
+    // loads, one wait), then the other pieces of split segments are added.
+    // Band 0, the largest, is loaded once the lowest band is in place, so its
+    // loads are in flight while the chain runs through the lower bands.
     float4 pv[kUpSlotsTotal];
 #pragma unroll
-    for (int h = 0; h < kMaxBands; ++h) {
+    for (int h = 0; h < kMaxBands; ++h)
 #pragma unroll
-        for (int i = 0; i < up_slots(h); ++i) {
-            pv[up_slot_base(h) + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            const int m = tid + kUpThreads * i;
-            if (h < H && m < up_pairs(n, h) && seg[h].npiece > 0)
-                pv[up_slot_base(h) + i] =
-                    *reinterpret_cast<const float4*>(bd->zw + seg[h].zoff + 2 * m);
-        }
-    }
+        for (int i = 0; i < up_slots(h); ++i) pv[up_slot_base(h) + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
-    for (int h = 0; h < kMaxBands; ++h) {
+    for (int h = 1; h < kMaxBands; ++h)
+        if (h < H) up_load(pv, h, zw, seg[h], bd->zstride[h], n, tid, 0);
+#pragma unroll
+    for (int h = 1; h < kMaxBands; ++h) {
         if (h >= H) continue;
         const SegDesc sg = seg[h];
-        for (int p = 1; p < sg.npiece; ++p) {
-#pragma unroll
-            for (int i = 0; i < up_slots(h); ++i) {
-                const int m = tid + kUpThreads * i;
-                if (m < up_pairs(n, h)) {
-                    const float4 u =
-                        *reinterpret_cast<const float4*>(bd->zw + sg.zoff + p * bd->zstride[h] + 2 * m);
-                    float4& v = pv[up_slot_base(h) + i];
-                    v.x += u.x;
-                    v.y += u.y;
-                    v.z += u.z;
-                    v.w += u.w;
-                }
-            }
-        }
+        for (int p = 1; p < sg.npiece; ++p) up_load(pv, h, zw, sg, bd->zstride[h], n, tid, p);
     }
 
     // lowest band: acc_{H-1} = z_{H-1}, placed after its history
     {
         const int nh = n >> (H - 1);
-        c32* hist = bd->uphist + ((int64_t)t * H + H - 1) * HU;
+        SPIIR_AS_GLOBAL c32* hist = gmem(bd->uphist) + ((int64_t)t * H + H - 1) * HU;
         for (int i = tid; i < HU; i += kUpThreads) cur[i] = hist[i];
 #pragma unroll
         for (int h = 1; h < kMaxBands; ++h) {
@@ -692,15 +744,18 @@ __global__ void __launch_bounds__(kUpThreads, 4) k_upadd(LaunchArgs args)
         __syncthreads();
         for (int i = tid; i < HU; i += kUpThreads) hist[i] = cur[nh + i];
     }
+    up_load(pv, 0, zw, seg[0], bd->zstride[0], n, tid, 0);
 
     const int ne = HU, no = tu / 2;  // even and odd polyphase tap counts
 #pragma unroll
     for (int h = kMaxBands - 2; h >= 0; --h) {
         if (h <= H - 2) {
             const int nh = n >> h, nlo = n >> (h + 1);
-            c32* hist = bd->uphist + ((int64_t)t * H + h) * HU;
+            SPIIR_AS_GLOBAL c32* hist = gmem(bd->uphist) + ((int64_t)t * H + h) * HU;
             if (h > 0)
                 for (int i = tid; i < HU; i += kUpThreads) nxt[i] = hl[(h - 1) * HU + i];
+            if (h == 0)
+                for (int p = 1; p < seg[0].npiece; ++p) up_load(pv, 0, zw, seg[0], bd->zstride[0], n, tid, p);
             // all of the thread's slots hold samples of this block
             const bool full = nlo >= kUpThreads * up_slots(h);
 #pragma unroll
@@ -778,22 +833,24 @@ __global__ void __launch_bounds__(kChainThreads) k_chain(LaunchArgs args)
     int r = 0;
     while (r + 1 < args.nreq && args.cum[r + 1] <= bid) ++r;
     const ReqArg& q = args.req[r];
-    const BankDev* bd = q.bd;
+    CBankDev* bd = cmem(q.bd);
     const int64_t g = (int64_t)(bid - args.cum[r]) * kChainThreads + threadIdx.x;
     if (g >= bd->n_slots) return;
-    const int h = bd->wg[g / ((int64_t)bd->F * bd->L)].band;
+    const int h = cmem(bd->wg)[g / ((int64_t)bd->F * bd->L)].band;
     const int nh = q.n >> h, lc = bd->lc[h];
-    const int64_t s0h = bd->clock[0] >> h;
+    const int64_t s0h = cmem(bd->clock)[0] >> h;
     const int64_t B = (s0h + lc - 1) / lc * lc;
     const int first_c = B == s0h ? 1 : 0;
     const int last_c = s0h + nh - 1 < B ? 0 : 1 + (int)((s0h + nh - 1 - B) / lc);
     const int64_t ns = bd->n_slots;
-    c32 st = bd->uend[first_c * ns + g];
-    const c32 al = bd->al[g];
+    const SPIIR_AS_CONST c32* uend = cmem(bd->uend);
+    SPIIR_AS_GLOBAL c32* schain = gmem(bd->schain);
+    c32 st = uend[first_c * ns + g];
+    const c32 al = cmem(bd->al)[g];
     for (int c = first_c + 1; c <= last_c; ++c) {
-        bd->schain[c * ns + g] = st;
+        schain[c * ns + g] = st;
         if (c < last_c) {
-            const c32 u = bd->uend[c * ns + g];
+            const c32 u = uend[c * ns + g];
             st = c32{fmaf(al.x, st.x, fmaf(-al.y, st.y, u.x)), fmaf(al.x, st.y, fmaf(al.y, st.x, u.y))};
         }
     }
