@@ -86,10 +86,13 @@ enum {
  *   carry_chunk           C: every C samples (absolute band index) the FP32
  *                         state is corrected by (a1^C - fl32(a1)^C) times the
  *                         state at the chunk start, computed in FP64 at
- *                         create; a multiple of 16 in [16, 1024]; 0 = 32.
- *   filters_per_lane      F in {1, 2, 4, 8}; 0 = library default.
+ *                         create; a power of two in [16, 1024]; 0 = 32.
+ *   filters_per_lane      F in {1, 2, 4, 6, 8}; 0 = library default (4 with
+ *                         the plain sum, 6 with the compensated sum).
  *   waves_per_group       wave64s per workgroup in [1, 16] ([1, 8] when
- *                         filters_per_lane is 8); 0 = default.
+ *                         filters_per_lane is 8); 0 = default (8, or 4 with
+ *                         6 or more filters per lane; fewer when a long
+ *                         delay window would not fit the LDS).
  *   device                HIP device ordinal the bank lives on.
  *   time_chunks           P in {0, 1, 2, 4, ..., 64}; 0 or 1 = off.  With
  *                         P > 1 each block is also split in time, so banks

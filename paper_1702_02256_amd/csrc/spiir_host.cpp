@@ -17,8 +17,14 @@ using namespace spiir;
 
 namespace {
 
+// Default launch shape.  The plain sum: 4 filters per lane, 8 waves per
+// group.  The compensated sum spends more per cross-lane addition, so it
+// gains from covering more filters per lane: 6 filters per lane, and with
+// them 4 waves per group (128 VGPRs, 4 groups per CU).
 constexpr int kDefaultF = 4;
+constexpr int kDefaultFComp = 6;
 constexpr int kDefaultW = 8;
+constexpr int kDefaultWWide = 4;  // with 6 or 8 filters per lane
 constexpr int kDefaultC = 32;
 constexpr int kSubBlock = 1024;     // samples per LDS window restage (largest tried)
 constexpr int kNoFit = 1;           // internal: this launch shape exceeds the LDS budget
@@ -26,6 +32,14 @@ constexpr int kXcapMax = 24576;     // LDS window, floats
 constexpr int kMaxLds = 160 * 1024;
 constexpr uint32_t kStateMagic = 0x53504952u;  // "SPIR"
 constexpr uint32_t kStateVersion = 1;
+
+int default_filters_per_lane(const spiir_bank_desc* d)
+{
+    if (d->filters_per_lane) return d->filters_per_lane;
+    return d->precision == SPIIR_FP32_COMPENSATED ? kDefaultFComp : kDefaultF;
+}
+
+int default_waves_per_group(int F) { return F >= 6 ? kDefaultWWide : kDefaultW; }
 
 int64_t next_pow2(int64_t v)
 {
@@ -74,9 +88,9 @@ int validate(const spiir_bank_desc* d)
     if (d->precision != SPIIR_FP32 && d->precision != SPIIR_FP32_COMPENSATED) return SPIIR_EINVAL;
     const int C = d->carry_chunk ? d->carry_chunk : kDefaultC;
     if (C < 16 || C > 1024 || (C & (C - 1)) != 0) return SPIIR_EINVAL;
-    const int F = d->filters_per_lane ? d->filters_per_lane : kDefaultF;
-    if (F != 1 && F != 2 && F != 4 && F != 8) return SPIIR_EINVAL;
-    const int W = d->waves_per_group ? d->waves_per_group : kDefaultW;
+    const int F = default_filters_per_lane(d);
+    if (F != 1 && F != 2 && F != 4 && F != 6 && F != 8) return SPIIR_EINVAL;
+    const int W = d->waves_per_group ? d->waves_per_group : default_waves_per_group(F);
     if (W < 1 || 64 * W > filter_max_threads(F)) return SPIIR_EINVAL;
     if (d->device < 0) return SPIIR_EINVAL;
     if (d->time_chunks < 0 || d->time_chunks > 64 || (d->time_chunks & (d->time_chunks - 1)) != 0)
@@ -110,7 +124,7 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
     p = Plan();
     p.T = d->n_templates;
     p.H = d->n_bands;
-    p.F = d->filters_per_lane ? d->filters_per_lane : kDefaultF;
+    p.F = default_filters_per_lane(d);
     p.W = W;
     p.L = 64 * p.W;
     p.C = d->carry_chunk ? d->carry_chunk : kDefaultC;
@@ -365,20 +379,21 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
     return SPIIR_OK;
 }
 
-// The launch shape: the caller's waves per group, or by default 8 waves and
-// fewer when a bank's delay window does not fit the LDS at 8 (long delays);
-// the window sub-block shrinks first.
+// The launch shape: the caller's waves per group, or by default the shape's
+// waves per group (8, or 4 with 6 or more filters per lane) and fewer when a
+// bank's delay window does not fit the LDS (long delays); the window
+// sub-block shrinks first.
 int make_plan(const spiir_bank_desc* d, Plan& p)
 {
     int rc = validate(d);
     if (rc) return rc;
-    const int F = d->filters_per_lane ? d->filters_per_lane : kDefaultF;
+    const int F = default_filters_per_lane(d);
     std::vector<int> ws;
     if (d->waves_per_group)
         ws.push_back(d->waves_per_group);
     else
-        for (int w : {kDefaultW, 4, 2, 1})
-            if (64 * w <= filter_max_threads(F)) ws.push_back(w);
+        for (int w : {8, 4, 2, 1})
+            if (w <= default_waves_per_group(F) && 64 * w <= filter_max_threads(F)) ws.push_back(w);
     for (int w : ws)
         for (int sub : {kSubBlock, 512, 256, 128, 64}) {
             rc = make_plan_shape(d, p, w, sub);

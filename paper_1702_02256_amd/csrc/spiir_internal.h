@@ -32,7 +32,7 @@ constexpr int filter_max_threads(int F) { return F >= 8 ? 512 : 1024; }
 // Waves per SIMD the compiler must leave room for (caps VGPRs at 512 / n):
 // with 4 filters and the plain sum a lane fits in 96 VGPRs without spilling,
 // so 5 waves; the compensated sum needs more, so 4.
-constexpr int filter_min_waves(int F, bool comp) { return F == 4 ? (comp ? 4 : 5) : 1; }
+constexpr int filter_min_waves(int F, bool comp) { return F == 4 ? (comp ? 4 : 5) : F == 6 ? 4 : 1; }
 
 struct alignas(8) c32 {
     float x, y;

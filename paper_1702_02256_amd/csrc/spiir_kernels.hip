@@ -55,6 +55,7 @@ typedef const SPIIR_AS_CONST BankDev CBankDev;
 // ---------------------------------------------------------------------------
 // Input staging and the downsample cascade (one workgroup per request).
 constexpr int kStageThreads = 1024;
+constexpr int kStageFastTaps = 32;  // decimator length with an unrolled path
 // LDS: cur [td-1 + max_block] | nxt [td-1 + max_block/2] | taps [td]
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
@@ -77,17 +78,26 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
     SPIIR_AS_GLOBAL float* rings = gmem(bd->rings);
     SPIIR_AS_GLOBAL float* ring0 = rings + bd->ring_off[0];
     const int64_t m0 = bd->ring_mask[0];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) ring0[(s0 + i) & m0] = x[i];
-    if (H == 1) return;
+    if (H == 1) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) ring0[(s0 + i) & m0] = x[i];
+        return;
+    }
 
     const int td = bd->td;
     const int hl = td - 1;
+    const SPIIR_AS_CONST float* tap = cmem(bd->hd);
     float* cur = sm;
     float* nxt = sm + hl + bd->max_block;
     float* hd = nxt + hl + bd->max_block / 2;
     for (int i = threadIdx.x; i < td; i += blockDim.x) hd[i] = cmem(bd->hd)[i];
     for (int i = threadIdx.x; i < hl; i += blockDim.x) cur[i] = ring0[(s0 - hl + i) & m0];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) cur[hl + i] = x[i];
+    // the block goes to the band-0 ring and to LDS (the ring slots of the
+    // history read above are not among the ones written here)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float v = x[i];
+        ring0[(s0 + i) & m0] = v;
+        cur[hl + i] = v;
+    }
     __syncthreads();
 
     for (int h = 1; h < H; ++h) {
@@ -101,7 +111,17 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
             // x_h[m] = sum_j h_d[j] x_{h-1}[2m - j]; cur[hl + i] holds x_{h-1} at block offset i
             const float* src = cur + hl + 2 * m;
             float s = 0.0f;
-            for (int j = 0; j < td; ++j) s = fmaf(hd[j], src[-j], s);
+            if (td == kStageFastTaps) {
+                // the common 32-tap decimator: taps as scalar loads, the window read
+                // first, then the multiply-adds in the same order as the loop below
+                float w[kStageFastTaps];
+#pragma unroll
+                for (int j = 0; j < kStageFastTaps; ++j) w[j] = src[-j];
+#pragma unroll
+                for (int j = 0; j < kStageFastTaps; ++j) s = fmaf(tap[j], w[j], s);
+            } else {
+                for (int j = 0; j < td; ++j) s = fmaf(hd[j], src[-j], s);
+            }
             nxt[hl + m] = s;
             ring[(s0h + m) & mk] = s;
         }
@@ -959,6 +979,8 @@ int allow_filter_lds()
     if (!e) e = allow_lds_t<2, true>();
     if (!e) e = allow_lds_t<4, false>();
     if (!e) e = allow_lds_t<4, true>();
+    if (!e) e = allow_lds_t<6, false>();
+    if (!e) e = allow_lds_t<6, true>();
     if (!e) e = allow_lds_t<8, false>();
     if (!e) e = allow_lds_t<8, true>();
     return e;
@@ -976,6 +998,8 @@ static int launch_filter_any(int F, int precision, const LaunchArgs& a, int nblo
                         : launch_filter_t<2, false, LOCAL>(a, nblocks, L, lds_bytes, s);
     case 4: return comp ? launch_filter_t<4, true, LOCAL>(a, nblocks, L, lds_bytes, s)
                         : launch_filter_t<4, false, LOCAL>(a, nblocks, L, lds_bytes, s);
+    case 6: return comp ? launch_filter_t<6, true, LOCAL>(a, nblocks, L, lds_bytes, s)
+                        : launch_filter_t<6, false, LOCAL>(a, nblocks, L, lds_bytes, s);
     case 8: return comp ? launch_filter_t<8, true, LOCAL>(a, nblocks, L, lds_bytes, s)
                         : launch_filter_t<8, false, LOCAL>(a, nblocks, L, lds_bytes, s);
     default: return (int)hipErrorInvalidValue;

@@ -165,6 +165,20 @@ def test_plan_time_chunks():
     assert S.spiir_plan(wl.bank, 4096, time_chunks=1)["footprint"] == p1["footprint"]
 
 
+def test_default_shape_follows_the_precision():
+    bank = W.config3(n_templates=8, n_blocks=1).bank
+    plain = S.spiir_plan(bank, 4096)
+    comp = S.spiir_plan(bank, 4096, precision="fp32_compensated")
+    assert (plain["filters_per_lane"], plain["lanes_per_group"]) == (4, 512)
+    assert (comp["filters_per_lane"], comp["lanes_per_group"]) == (6, 256)
+    # an explicit F keeps its own default width; explicit shapes are kept
+    assert S.spiir_plan(bank, 4096, filters_per_lane=8)["lanes_per_group"] == 256
+    assert S.spiir_plan(bank, 4096, precision="fp32_compensated", filters_per_lane=4,
+                        waves_per_group=8)["lanes_per_group"] == 512
+    # every filter slot is a filter or padding: F = 6 packs segments in lanes of 6
+    assert comp["filter_slots"] % 6 == 0 and comp["filter_slots"] >= comp["total_filters"]
+
+
 def test_long_delays_fall_back_to_a_smaller_launch_shape():
     # a delay window of 16383 samples does not fit the LDS next to 8-wave reduction
     # buffers; the default shape steps down instead of refusing the bank
