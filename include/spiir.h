@@ -259,8 +259,8 @@ int spiir_reset(spiir_bank* bank);
 /* spiir_state_size — bytes of the blob spiir_save_state writes. */
 int spiir_state_size(const spiir_bank* bank, size_t* bytes);
 
-/* spiir_save_state — copy the carried state (filter states, chunk-start
- * states, input histories, up-chain histories, flags, sample count) into
+/* spiir_save_state — copy the carried state (filter states, pending carry
+ * corrections, input histories, up-chain histories, flags, sample count) into
  * host_buf (spiir_state_size bytes).  Waits for the bank's work. */
 int spiir_save_state(spiir_bank* bank, void* host_buf, void* hip_stream);
 

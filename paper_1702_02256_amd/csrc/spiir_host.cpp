@@ -31,7 +31,7 @@ constexpr int kNoFit = 1;           // internal: this launch shape exceeds the L
 constexpr int kXcapMax = 24576;     // LDS window, floats
 constexpr int kMaxLds = 160 * 1024;
 constexpr uint32_t kStateMagic = 0x53504952u;  // "SPIR"
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;  // 2: the carried chunk value is the pending correction
 
 int default_filters_per_lane(const spiir_bank_desc* d)
 {

@@ -92,7 +92,7 @@ struct BankDev {
     const c32* dc;                  // per slot: a1^C - fl32(a1)^C (FP64 -> FP32)
     const int32_t* off;             // per slot: delay d (band samples)
     c32* y;                         // per slot: state y[k-1]
-    c32* ys;                        // per slot: state at the current chunk start
+    c32* ys;                        // per slot: pending carry correction dC * (state at the chunk start)
     float* rings;                   // per-band input history rings
     const float* hd;
     const float* hu;
@@ -111,7 +111,7 @@ struct BankDev {
     const c32* al;                  // per slot: a1^lc (FP64 -> FP32), same form as `a`
     c32* uend;                      // [P+1][n_slots] chunk end states from zero start
     c32* schain;                    // [P+1][n_slots] chained chunk start states
-    c32* ys0;                       // [n_slots] chunk-start state entering the block
+    c32* ys0;                       // [n_slots] pending carry correction entering the block
 };
 
 struct ReqArg {

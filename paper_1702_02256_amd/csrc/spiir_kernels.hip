@@ -312,15 +312,16 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
         prun[p] = make_int2(pd.run0, pd.run1);
     }
 
-    float ar[F], ai[F], br[F], bi[F], dr[F], di[F], yr[F], yi[F], sr[F], si[F];
+    float ar[F], ai[F], br[F], bi[F], dr[F], di[F], yr[F], yi[F], ur[F], ui[F];
     int dl[F];
-    // Start state.  The first chunk starts from the carried state; when the
-    // block has more than one chunk, the end-state pass saves that state
-    // (schain row of the first chunk, ys0) for the filter pass, whose last
-    // chunk overwrites the carried state while the first may still read it.
-    // A later chunk starts from zero in the end-state pass and from its chained
-    // state in the filter pass (its start is a carry-chunk boundary, so y and
-    // the chunk-start state agree).
+    // Start state: y and the pending carry correction u = dC * (y at the start
+    // of the current carry chunk), which is added to y at the chunk's end.
+    // The first chunk starts from the carried state; when the block has more
+    // than one chunk, the end-state pass saves that state (schain row of the
+    // first chunk, ys0) for the filter pass, whose last chunk overwrites the
+    // carried state while the first may still read it.  A later chunk starts
+    // from zero in the end-state pass and from its chained state in the
+    // filter pass; its start is a carry-chunk boundary, so u = dC * y there.
     const c32* ysrc = bd->y;
     const c32* yssrc = bd->ys;
     if (!ch.first) ysrc = yssrc = bd->schain + (int64_t)tc * bd->n_slots;
@@ -344,7 +345,12 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
         br[f] = b.x; bi[f] = b.y;
         dr[f] = d.x; di[f] = d.y;
         yr[f] = y.x; yi[f] = y.y;
-        sr[f] = ys.x; si[f] = ys.y;
+        if (ch.first) {
+            ur[f] = ys.x; ui[f] = ys.y;
+        } else {
+            ur[f] = fmaf(d.x, y.x, -d.y * y.y);
+            ui[f] = fmaf(d.x, y.y, d.y * y.x);
+        }
         dl[f] = cmem(bd->off)[g];
     }
     __syncthreads();
@@ -423,14 +429,16 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
                 tile_partial<F, !LOCAL>(xp, cnt, pcol, ar, ai, br, bi, yr, yi);
             }
 
-            // carry correction after the last sample of an absolute chunk of C samples
+            // carry correction after the last sample of an absolute chunk of C
+            // samples: add the pending correction, then form the next chunk's
+            // from the corrected state (each value keeps its own registers)
             if (((kabs + cnt) & cmask) == 0) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
-                    const float nr = fmaf(dr[f], sr[f], fmaf(-di[f], si[f], yr[f]));
-                    const float ni = fmaf(dr[f], si[f], fmaf(di[f], sr[f], yi[f]));
-                    yr[f] = nr; yi[f] = ni;
-                    sr[f] = nr; si[f] = ni;
+                    yr[f] += ur[f];
+                    yi[f] += ui[f];
+                    ur[f] = fmaf(dr[f], yr[f], -di[f] * yi[f]);
+                    ui[f] = fmaf(dr[f], yi[f], di[f] * yr[f]);
                 }
             }
 
@@ -546,7 +554,7 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
     for (int f = 0; f < F; ++f) {
         const int64_t g = wg.slot_base + (int64_t)f * L + tid;
         gmem(bd->y)[g] = c32{yr[f], yi[f]};
-        gmem(bd->ys)[g] = c32{sr[f], si[f]};
+        gmem(bd->ys)[g] = c32{ur[f], ui[f]};
         bad |= !(isfinite(yr[f]) && isfinite(yi[f]));
     }
     if (bad) {
