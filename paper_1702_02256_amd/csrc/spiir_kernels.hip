@@ -565,11 +565,13 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
 
 // ---------------------------------------------------------------------------
 // Upsample-and-add chain, one workgroup of kUpThreads per (request, template).
-// Every band's piece sums are fetched into registers first (one burst of
-// independent loads), then the chain runs from LDS, lowest band first.  A
-// thread owns low-rate samples m = tid + kUpThreads*i of acc_{h+1} and writes
-// both polyphase outputs acc_h[2m] and acc_h[2m+1] from the same window.
-// LDS: e0 [hu_len + max_block/2] c32 | e1 [same] | taps [tu]
+// The piece sums of bands 1.. are fetched into registers first (one burst of
+// independent loads), band 0's once the lowest band is in LDS, so they arrive
+// while the chain runs from LDS, lowest band first.  A thread owns low-rate
+// samples m = tid + kUpThreads*i of acc_{h+1} and writes both polyphase
+// outputs acc_h[2m] and acc_h[2m+1] from the same window.
+// LDS: cur [hu_len + max_block/2] c32 | nxt [same] | histories of bands
+// 1..H-2 [(H-2) hu_len] c32 | taps [tu]
 // ---------------------------------------------------------------------------
 constexpr int kUpThreads = 256;
 constexpr int kUpFastTaps = 32;  // interpolator length with an unrolled path
@@ -702,10 +704,9 @@ __global__ void __launch_bounds__(kUpThreads, 4) k_upadd(LaunchArgs args)
     SPIIR_AS_GLOBAL c32* zrow = q.z ? gmem(q.z) + (int64_t)t * q.ldz : nullptr;
     const bool peaks = q.peaks != nullptr;
     PeakAcc acc;
-    // The common 32-tap interpolator runs with its taps in registers (read
-    // before any store, so as uniform scalar loads) and the tap loop unrolled;
-    // other lengths read the taps from LDS.  Both add the terms in the same
-    // order, so they give the same bits.
+    // The common 32-tap interpolator reads its taps as uniform scalar loads
+    // and runs the tap loop unrolled; other lengths read the taps from LDS.
+    // Both add the terms in the same order, so they give the same bits.
     const bool taps32 = tu == kUpFastTaps;
     const SPIIR_AS_CONST float* tap = cmem(bd->hu);
 
