@@ -93,6 +93,24 @@ def test_config3_subset():
     check(zg, zr, label="cfg3-sub")
 
 
+def test_long_stream_error_is_stationary():
+    """64 s of the multi-rate bank in 1 s blocks (the stream length of the multi-rate
+    workload): the FP32 state carried across blocks does not drift away from the
+    FP64 oracle; the error of the last 8 s is of the size of the first 8 s."""
+    tsel = [3, 1500, 4000]
+    wl = W.config3(templates=tsel, n_blocks=64)
+    x = wl.stream()
+    _say("cfg3 long stream: 3 templates x 7 bands, 64 blocks of 4096 (64 s)")
+    zg = run_gpu(wl.bank, x, [4096] * 64, precision="fp32_compensated")
+    zr = oracle.run_stream(wl.bank, x)
+    check(zg, zr, label="cfg3-64s")
+    win = 8 * 4096
+    first = rel_err(zg[:, :win], zr[:, :win])
+    last = rel_err(zg[:, -win:], zr[:, -win:])
+    _say(f"first 8 s {first.max():.3e}, last 8 s {last.max():.3e}")
+    assert np.all(last <= np.maximum(3.0 * first, 2e-6)), (first, last)
+
+
 def test_config4_subset_uneven():
     tsel = list(range(24))
     wl = W.config4(templates=tsel, n_blocks=2)
@@ -334,6 +352,44 @@ def test_batch_equals_alone_bitwise():
     torch.cuda.synchronize()
     for i in range(3):
         assert np.array_equal(zt[i].cpu().numpy().astype(np.complex128), alone[i]), i
+        banks[i].destroy()
+
+
+def test_mixed_batch_equals_alone_bitwise():
+    """One batch over a single-rate bank, a multi-rate bank with the common 32-tap
+    resamplers, one with 15-tap resamplers (the generic up-add path) and a bank
+    split in time, all compensated (default shape); each result is the bank's own."""
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    rng = np.random.default_rng(44)
+    tabs = [
+        W.random_bank(41, rng.integers(5, 90, size=(3, 1)).astype(np.int32), 2048, [900]),
+        W.random_bank(42, rng.integers(5, 90, size=(4, 4)).astype(np.int32), 2048,
+                      W.multirate_dmax(2048, 4)),
+        W.random_bank(43, rng.integers(5, 90, size=(2, 3)).astype(np.int32), 2048,
+                      W.multirate_dmax(2048, 3), n_taps_down=15, n_taps_up=15),
+        W.random_bank(45, rng.integers(5, 90, size=(2, 1)).astype(np.int32), 2048, [700]),
+    ]
+    kws = [{}, {}, {}, {"time_chunks": 8}]
+    xs = [W.noise_stream(50 + i, 4096) for i in range(4)]
+    lens = [1024, 2048, 512, 2048]
+    kw0 = dict(precision="fp32_compensated")
+    alone = [run_gpu(tabs[i], xs[i], [lens[i], lens[i]], max_block=2048, **kw0, **kws[i])
+             for i in range(4)]
+    banks = [S.Bank(tabs[i], 2048, **kw0, **kws[i]) for i in range(4)]
+    for blk in range(2):
+        xt = [torch.from_numpy(xs[i][blk * lens[i]:(blk + 1) * lens[i]].astype(np.float32)).cuda()
+              for i in range(4)]
+        zt = [torch.zeros((tabs[i].n_templates, lens[i]), dtype=torch.complex64, device="cuda")
+              for i in range(4)]
+        S.spiir_process_batch([(banks[i], xt[i], zt[i]) for i in range(4)])
+        torch.cuda.synchronize()
+        for i in range(4):
+            got = zt[i].cpu().numpy().astype(np.complex128)
+            assert np.array_equal(got, alone[i][:, blk * lens[i]:(blk + 1) * lens[i]]), (blk, i)
+    for i in range(4):
+        zr = oracle.run_stream(tabs[i], xs[i][:2 * lens[i]])
+        check(alone[i], zr, label=f"mixed-batch bank {i}")
         banks[i].destroy()
 
 
