@@ -239,6 +239,9 @@ def serving_bench(args, S, W, torch, np):
         summ = st.summary()
         summ["speed"] = speed
         summ["sustained"] = bool(st.wall <= last + 0.25)
+        print(f"serving {policy} at {speed}x: {summ.get('blocks')} blocks, p99 "
+              f"{summ.get('p99_ms', float('nan')):.1f} ms, sustained {summ['sustained']}",
+              file=sys.stderr, flush=True)
         return summ
 
     rt = {pol: serve(pol, 1.0, dur) for pol in ("batched", "plain")}
@@ -317,6 +320,8 @@ def main():
     ap.add_argument("--carry-chunk", type=int, default=0)
     ap.add_argument("--time-chunks", type=int, default=0,
                     help="split every block in time into this many chunks (small banks)")
+    ap.add_argument("--window-copies", type=int, default=0, choices=[0, 1, 2],
+                    help="LDS copies of the filter kernel's input window (0 = library choice)")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp32_compensated"],
                     help="summation over filters (default: compensated for the multi-rate "
                          "configurations 3 and 5, which name it, plain FP32 otherwise)")
@@ -380,7 +385,8 @@ def main():
     stream = torch.cuda.Stream()
     bank = S.Bank(tb, block, stream=stream, precision=args.precision,
                   carry_chunk=args.carry_chunk, filters_per_lane=args.filters_per_lane,
-                  waves_per_group=args.waves_per_group, time_chunks=args.time_chunks)
+                  waves_per_group=args.waves_per_group, time_chunks=args.time_chunks,
+                  window_copies=args.window_copies)
     z = torch.zeros((T, block), dtype=torch.complex64, device="cuda")
     fs_block = tb.filter_samples_per_block(block)
     flops = W.algorithmic_flops(tb, block)
@@ -480,6 +486,7 @@ def main():
             "lanes_per_group": plan["lanes_per_group"],
             "carry_chunk": plan["carry_chunk"],
             "time_chunks": plan["time_chunks"],
+            "window_copies": plan["window_copies"],
         },
         "real_time_templates": T * block_s / (ms_step * 1e-3),
         "block_latency_ms": {"mean": float(lat.mean()), "p50": float(np.percentile(lat, 50)),

@@ -106,6 +106,13 @@ enum {
  *                         filter pass runs every chunk from its start state.
  *                         Results differ from P = 1 by rounding only (the
  *                         bitwise block-split invariance holds for P <= 1).
+ *   window_copies         1 or 2; 0 = chosen by the library.  The filter
+ *                         kernel keeps each band's input window in LDS, as
+ *                         two copies shifted by one sample (each filter reads
+ *                         a sample pair with one aligned 64-bit access) or as
+ *                         one (two 32-bit accesses, half the LDS, so long
+ *                         delay windows leave room for more workgroups per
+ *                         compute unit).  Results do not depend on it.
  */
 typedef struct {
     int32_t n_templates;
@@ -126,6 +133,7 @@ typedef struct {
     int32_t waves_per_group;
     int32_t device;
     int32_t time_chunks;
+    int32_t window_copies;
 } spiir_bank_desc;
 
 #define SPIIR_MAX_BANDS 12
@@ -298,6 +306,7 @@ typedef struct {
     int32_t carry_chunk;      /* C                                             */
     size_t footprint;         /* device bytes spiir_create allocates           */
     int32_t time_chunks;      /* P (1 = no time split)                         */
+    int32_t window_copies;    /* LDS copies of the input window (1 or 2)       */
 } spiir_plan_info;
 
 int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info);

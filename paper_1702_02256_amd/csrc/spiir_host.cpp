@@ -30,6 +30,7 @@ constexpr int kSubBlock = 1024;     // samples per LDS window restage (largest t
 constexpr int kNoFit = 1;           // internal: this launch shape exceeds the LDS budget
 constexpr int kXcapMax = 24576;     // LDS window, floats
 constexpr int kMaxLds = 160 * 1024;
+constexpr int kComputeUnits = 256;  // MI355X
 constexpr uint32_t kStateMagic = 0x53504952u;  // "SPIR"
 constexpr uint32_t kStateVersion = 2;  // 2: the carried chunk value is the pending correction
 
@@ -53,7 +54,7 @@ struct Plan {
     int td = 0, tu = 0, hu_len = 0, max_block = 0, mb_inner = 0;
     int P = 1;
     int lc[SPIIR_MAX_BANDS] = {};
-    int xcap = 0;
+    int xcap = 0, copies = 2;
     int nrun_max = 1, npiece_max = 1;
     int lds_filter = 0, lds_stage = 0, lds_up = 0;
     int64_t total_filters = 0, n_slots = 0, zw_elems = 0, ring_total = 0;
@@ -95,6 +96,7 @@ int validate(const spiir_bank_desc* d)
     if (d->device < 0) return SPIIR_EINVAL;
     if (d->time_chunks < 0 || d->time_chunks > 64 || (d->time_chunks & (d->time_chunks - 1)) != 0)
         return SPIIR_EINVAL;
+    if (d->window_copies < 0 || d->window_copies > 2) return SPIIR_EINVAL;
     int64_t total = 0;
     for (int64_t s = 0; s < (int64_t)d->n_templates * H; ++s) {
         if (d->n_filters[s] < 0) return SPIIR_EINVAL;
@@ -119,7 +121,7 @@ int validate(const spiir_bank_desc* d)
 // workgroups of L lanes; a segment crossing a workgroup boundary becomes two
 // pieces.  Padding lanes and slots carry zero coefficients (their outputs are
 // exactly zero) and belong to the last piece of their workgroup.
-int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
+int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub, int copies)
 {
     p = Plan();
     p.T = d->n_templates;
@@ -158,15 +160,17 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
             for (int l = 0; l < d->n_filters[t * H + h]; ++l)
                 p.maxd_band[h] = std::max(p.maxd_band[h], (int)d->delay[moff[t * H + h] + l]);
 
-    // LDS window: two copies (x and x shifted by one sample) of up to
-    // maxd + S + 64 samples each, S = min(block, sub); a copy's size is
-    // 32 mod 64 dwords so that the second copy starts 32 banks after the first.
+    // LDS window: one copy, or two (x and x shifted by one sample), of up to
+    // maxd + S + 64 samples each, S = min(block, sub); with two, a copy's size
+    // is 32 mod 64 dwords so that the second copy starts 32 banks after the
+    // first.
     int X = 0;
     for (int h = 0; h < H; ++h)
         X = std::max(X, p.maxd_band[h] + std::min(sub, p.mb_inner >> h) + 65);
-    X = ((X + 63) & ~63) + 32;
+    X = copies == 2 ? ((X + 63) & ~63) + 32 : ((X + 63) & ~63);
     if (X > kXcapMax) return kNoFit;
     p.xcap = X;
+    p.copies = copies;
     p.S.assign(H, 0);
     p.zstride.assign(H, 0);
     for (int h = 0; h < H; ++h) p.zstride[h] = (int64_t)(((p.mb_inner >> h) + 1) & ~1);
@@ -244,16 +248,21 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
         open_wg();
     };
 
-    // Bank-aware placement.  A full tile reads, per filter, the 8-byte pair at
-    // x[k - d] from the window copy of d's parity; with the window origin a
-    // multiple of 64 samples and the copies 32 banks apart, that read occupies
-    // the bank pair (15*(d & 1) - (d >> 1)) mod 32 plus a term common to all
-    // lanes.  64-bit reads are served 32 lanes at a time over 64 banks, so
-    // within one half-wave and slot the lanes conflict exactly when their
-    // classes agree.  Each segment's filters are dealt to its (lane, slot)
-    // positions greedily, picking for every position a class that is least
-    // used so far in that row.
+    // Bank-aware placement.  With two window copies a full tile reads, per
+    // filter, the 8-byte pair at x[k - d] from the copy of d's parity; with
+    // the window origin a multiple of 64 samples and the copies 32 banks
+    // apart, that read occupies the bank pair (15*(d & 1) - (d >> 1)) mod 32
+    // plus a term common to all lanes.  64-bit reads are served 32 lanes at a
+    // time over 64 banks, so within one half-wave and slot the lanes conflict
+    // exactly when their classes agree.  With one copy the tile reads the
+    // words x[k - d] and x[k + 1 - d] (banks (-d) mod 64 and the next, plus the
+    // common term, 32 lanes at a time): lanes in distinct classes never share
+    // a bank there either, so the same placement serves both layouts and the
+    // summation order, hence the output, does not depend on the layout.  Each
+    // segment's filters are dealt to its (lane, slot) positions greedily,
+    // picking for every position a class that is least used so far in that row.
     constexpr int kBanks = 32;
+    auto bank_class = [](int dj) { return (15 * (dj & 1) - (dj >> 1)) & (kBanks - 1); };
     const int halves = L / 32;
     using Counts = std::vector<uint16_t>;  // [F][halves][kBanks]
     auto fresh_counts = [&]() { return Counts((size_t)F * halves * kBanks, 0); };
@@ -299,7 +308,7 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
             std::vector<std::vector<int>> bucket(kBanks);
             for (int j = M - 1; j >= 0; --j) {
                 const int dj = d->delay[base + j];
-                bucket[(15 * (dj & 1) - (dj >> 1)) & (kBanks - 1)].push_back(j);
+                bucket[bank_class(dj)].push_back(j);
             }
             std::vector<int> assign((size_t)nl * F, -1);
             for (int f = 0; f < F; ++f)
@@ -358,7 +367,7 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
     for (size_t i = 0; i < p.lane_meta.size(); ++i)
         if ((p.lane_meta[i] & 0xffff) != kSlotNone && (i & 1) == 0) return SPIIR_EINVAL;
 
-    p.lds_filter = 2 * p.xcap * 4 + (L / 2) * (kTile + 1) * 8 + 2 * kTile * p.nrun_max * 8 + p.npiece_max * 8 +
+    p.lds_filter = p.copies * p.xcap * 4 + (L / 2) * (kTile + 1) * 8 + 2 * kTile * p.nrun_max * 8 + p.npiece_max * 8 +
                    L * 4 + p.npiece_max * 8;
     p.lds_stage = ((p.td - 1) + p.mb_inner + (p.td - 1) + p.mb_inner / 2 + p.td) * 4;
     p.lds_up = (2 * (p.hu_len + p.mb_inner / 2) + std::max(p.H - 2, 0) * p.hu_len) * 8 + p.tu * 4;
@@ -379,10 +388,51 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub)
     return SPIIR_OK;
 }
 
+// Waves per SIMD the registers of the filter kernel allow (from the compiled
+// kernels' VGPR counts: 512 per SIMD lane over the rounded allocation); used
+// only to rank launch shapes.
+int filter_reg_waves(int F, bool comp)
+{
+    switch (F) {
+    case 1: return comp ? 7 : 8;
+    case 2: return 6;
+    case 4: return comp ? 4 : 5;
+    case 6: return 4;
+    default: return 2;
+    }
+}
+
+// Filter workgroups a compute unit runs at once for this bank: what the LDS
+// and the registers allow, and no more than the bank's workgroups spread
+// over the device's compute units.
+int filter_groups_per_cu(const Plan& p)
+{
+    const int by_lds = kMaxLds / std::max(p.lds_filter, 1);
+    const int by_regs = 4 * filter_reg_waves(p.F, p.precision == SPIIR_FP32_COMPENSATED) / p.W;
+    const int64_t groups = (int64_t)p.wg.size() * p.P;
+    const int by_bank = (int)std::min<int64_t>((groups + kComputeUnits - 1) / kComputeUnits, 1 << 20);
+    return std::min(std::min(by_lds, by_regs), by_bank);
+}
+
+// Largest window sub-block for which the shape fits the LDS.
+int fit_shape(const spiir_bank_desc* d, Plan& p, int W, int copies)
+{
+    int rc = kNoFit;
+    for (int sub : {kSubBlock, 512, 256, 128, 64}) {
+        rc = make_plan_shape(d, p, W, sub, copies);
+        if (rc != kNoFit) return rc;
+    }
+    return rc;
+}
+
 // The launch shape: the caller's waves per group, or by default the shape's
 // waves per group (8, or 4 with 6 or more filters per lane) and fewer when a
 // bank's delay window does not fit the LDS (long delays); the window
-// sub-block shrinks first.
+// sub-block shrinks first.  The input window is held twice unless the caller
+// asks for one copy, or a single copy lets a compute unit run more of the
+// bank's waves where two leave it fewer than 3 per SIMD (long delay windows
+// in banks large enough to fill the device); a copy less costs about 4% in
+// LDS reads, more waves per SIMD gain more.
 int make_plan(const spiir_bank_desc* d, Plan& p)
 {
     int rc = validate(d);
@@ -394,11 +444,26 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
     else
         for (int w : {8, 4, 2, 1})
             if (w <= default_waves_per_group(F) && 64 * w <= filter_max_threads(F)) ws.push_back(w);
-    for (int w : ws)
-        for (int sub : {kSubBlock, 512, 256, 128, 64}) {
-            rc = make_plan_shape(d, p, w, sub);
+    for (int w : ws) {
+        if (d->window_copies) {
+            rc = fit_shape(d, p, w, d->window_copies);
             if (rc != kNoFit) return rc;
+            continue;
         }
+        rc = fit_shape(d, p, w, 2);
+        if (rc != kNoFit && rc != SPIIR_OK) return rc;
+        const int waves2 = rc == SPIIR_OK ? filter_groups_per_cu(p) * w : 0;
+        if (waves2 >= 12) return SPIIR_OK;  // the one-copy plan is not needed
+        Plan one;
+        const int rc1 = fit_shape(d, one, w, 1);
+        if (rc1 == kNoFit) {
+            if (rc == kNoFit) continue;
+            return SPIIR_OK;
+        }
+        if (rc1 != SPIIR_OK) return rc1;
+        if (filter_groups_per_cu(one) * w > waves2) p = std::move(one);
+        return SPIIR_OK;
+    }
     return SPIIR_EINVAL;
 }
 
@@ -727,6 +792,7 @@ int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info)
     info->carry_chunk = p.C;
     info->footprint = p.footprint;
     info->time_chunks = p.P;
+    info->window_copies = p.copies;
     return SPIIR_OK;
 }
 
@@ -833,6 +899,7 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     bd.hu_len = p.hu_len;
     bd.max_block = p.mb_inner;
     bd.xcap = p.xcap;
+    bd.copies = p.copies;
     bd.nrun_max = p.nrun_max;
     bd.npiece_max = p.npiece_max;
     for (int h = 0; h < p.H; ++h) {

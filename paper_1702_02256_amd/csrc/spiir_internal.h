@@ -73,6 +73,7 @@ struct BankDev {
     int32_t T, H, L, F, C, precision;
     int32_t td, tu, hu_len, max_block;
     int32_t xcap;                   // LDS capacity of one window copy, floats
+    int32_t copies;                 // window copies in LDS (1 or 2)
     int32_t nrun_max;               // level-2 run slots per tile row
     int32_t npiece_max;
     int32_t pad0;

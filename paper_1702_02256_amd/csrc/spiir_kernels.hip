@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(LaunchArgs args)
 
 // ---------------------------------------------------------------------------
 // The filter bank.
-// LDS: E0 [xcap] | E1 [xcap] | pbuf [L/2][kTile+1] c32 | l2 2 x [kTile][nrun_max] c32 |
+// LDS: E0 [xcap] | E1 [xcap] (two copies only) | pbuf [L/2][kTile+1] c32 | l2 2 x [kTile][nrun_max] c32 |
 //      pzoff [npiece_max] i64 | lmeta [L] i32 | prun [npiece_max] int2
 // ---------------------------------------------------------------------------
 // value of the other lane of the pair (lane ^ 1), via DPP quad_perm [1,0,3,2]
@@ -212,6 +212,26 @@ __device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* _
         }
         one_step<F, SUM>(xa, pcol, 2 * jj, ar, ai, br, bi, yr, yi);
         one_step<F, SUM>(xb, pcol, 2 * jj + 1, ar, ai, br, bi, yr, yi);
+    }
+}
+
+// A full tile from a single window copy: x1[f] points at x[k - d]; each
+// sample is one 32-bit read (the compiler pairs them into two-word reads).
+template <int F, bool SUM>
+__device__ __forceinline__ void tile_full1(const float* const (&xp)[F], float* __restrict__ pcol,
+                                           const float (&ar)[F], const float (&ai)[F],
+                                           const float (&br)[F], const float (&bi)[F],
+                                           float (&yr)[F], float (&yi)[F])
+{
+    const float* __restrict__ x1[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) x1[f] = xp[f];
+#pragma unroll
+    for (int j = 0; j < kTile; ++j) {
+        float xv[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) xv[f] = x1[f][j];
+        one_step<F, SUM>(xv, pcol, j, ar, ai, br, bi, yr, yi);
     }
 }
 
@@ -295,11 +315,12 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
     const int64_t cmask = bd->C - 1;
     const int nrun = bd->nrun_max;
 
-    // The x window is held twice: E0[m] = x[origin + m] and E1[m] = x[origin + 1 + m],
-    // origin a multiple of 64 absolute samples; E1 starts 32 banks after E0.
+    // The x window is held twice, E0[m] = x[origin + m] and E1[m] = x[origin + 1 + m]
+    // (origin a multiple of 64 absolute samples, E1 32 banks after E0), or once (E0).
+    const bool two_copies = bd->copies == 2;
     float* E0 = sm;
     float* E1 = sm + bd->xcap;
-    c32* pbuf = reinterpret_cast<c32*>(sm + 2 * bd->xcap);
+    c32* pbuf = reinterpret_cast<c32*>(sm + bd->copies * bd->xcap);
     c32* l2buf = pbuf + (L / 2) * (kTile + 1);  // two tile buffers of run sums
     long long* pzoff = reinterpret_cast<long long*>(l2buf + 2 * kTile * nrun);
     int* lmeta = reinterpret_cast<int*>(pzoff + bd->npiece_max);
@@ -403,7 +424,7 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
             for (int u = 0; u < kStageBatch; ++u) {
                 const int i = i0 + u * L;
                 if (i < wn) E0[i] = v[u];
-                if (i > 0 && i <= wn) E1[i - 1] = v[u];
+                if (two_copies && i > 0 && i <= wn) E1[i - 1] = v[u];
             }
         }
         __syncthreads();
@@ -414,7 +435,7 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
             int cnt = kTile - (int)(kabs & (kTile - 1));
             if (cnt > kb + sub - k) cnt = kb + sub - k;
             const int rel = (int)(kabs - origin);  // window position of sample k
-            if (cnt == kTile) {
+            if (cnt == kTile && two_copies) {
                 const float2* xp[F];
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
@@ -422,6 +443,11 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
                     xp[f] = reinterpret_cast<const float2*>((par ? E1 : E0) + (rel - dl[f] - par));
                 }
                 tile_full<F, !LOCAL>(xp, pcol, ar, ai, br, bi, yr, yi);
+            } else if (cnt == kTile) {
+                const float* xp[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) xp[f] = E0 + (rel - dl[f]);
+                tile_full1<F, !LOCAL>(xp, pcol, ar, ai, br, bi, yr, yi);
             } else {
                 const float* xp[F];
 #pragma unroll

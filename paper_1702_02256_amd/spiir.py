@@ -52,6 +52,7 @@ class BankDesc(C.Structure):
         ("waves_per_group", C.c_int32),
         ("device", C.c_int32),
         ("time_chunks", C.c_int32),
+        ("window_copies", C.c_int32),
     ]
 
 
@@ -77,6 +78,7 @@ class PlanInfo(C.Structure):
         ("carry_chunk", C.c_int32),
         ("footprint", C.c_size_t),
         ("time_chunks", C.c_int32),
+        ("window_copies", C.c_int32),
     ]
 
 
@@ -163,7 +165,7 @@ class _DescHolder:
     """A BankDesc plus the numpy arrays its pointers refer to."""
 
     def __init__(self, tables, max_block, precision="fp32", carry_chunk=0, filters_per_lane=0,
-                 waves_per_group=0, device=0, time_chunks=0):
+                 waves_per_group=0, device=0, time_chunks=0, window_copies=0):
         self.nf = np.ascontiguousarray(tables.n_filters.reshape(-1), dtype=np.int32)
         self.a1 = np.ascontiguousarray(np.asarray(tables.a1, np.complex128)).view(np.float64)
         self.b0 = np.ascontiguousarray(np.asarray(tables.b0, np.complex128)).view(np.float64)
@@ -182,7 +184,7 @@ class _DescHolder:
             n_taps_up=len(self.hu), h_up=dp(self.hu),
             max_block=int(max_block), precision=prec, carry_chunk=int(carry_chunk),
             filters_per_lane=int(filters_per_lane), waves_per_group=int(waves_per_group),
-            device=int(device), time_chunks=int(time_chunks))
+            device=int(device), time_chunks=int(time_chunks), window_copies=int(window_copies))
 
 
 # ---------------------------------------------------------------- C-named functions
@@ -322,17 +324,17 @@ class Bank:
     """One template bank bound to one input stream (owns its device memory)."""
 
     def __init__(self, tables, max_block, stream=None, precision="fp32", carry_chunk=0,
-                 filters_per_lane=0, waves_per_group=0, device=0, time_chunks=0):
+                 filters_per_lane=0, waves_per_group=0, device=0, time_chunks=0, window_copies=0):
         lib = load_library()
         self._lib = lib
         hold = _DescHolder(tables, max_block, precision, carry_chunk, filters_per_lane,
-                           waves_per_group, device, time_chunks)
+                           waves_per_group, device, time_chunks, window_copies)
         self.n_templates = int(tables.n_filters.shape[0])
         self.n_bands = int(tables.n_filters.shape[1])
         self.max_block = int(max_block)
         self.plan = spiir_plan(tables, max_block, precision=precision, carry_chunk=carry_chunk,
                                filters_per_lane=filters_per_lane, waves_per_group=waves_per_group,
-                               device=device, time_chunks=time_chunks)
+                               device=device, time_chunks=time_chunks, window_copies=window_copies)
         h = C.c_void_p()
         s = _stream_handle(stream) if stream is not None else C.c_void_p(0)
         _check(lib.spiir_create(C.byref(hold.desc), s, C.byref(h)), "spiir_create")

@@ -92,7 +92,7 @@ def test_footprint_matches_plan_and_scales():
 
 @pytest.mark.parametrize("field,value", [
     ("n_bands", 0), ("n_bands", 13), ("max_block", 0), ("max_block", 1023 + 2),
-    ("precision", 7), ("carry_chunk", 48), ("carry_chunk", 8), ("filters_per_lane", 3),
+    ("precision", 7), ("carry_chunk", 48), ("carry_chunk", 8), ("filters_per_lane", 3), ("window_copies", 3),
     ("waves_per_group", 17), ("base_rate_hz", 0), ("n_templates", 0), ("device", -1),
     ("time_chunks", 3), ("time_chunks", 128), ("time_chunks", -1),
 ])
@@ -179,15 +179,35 @@ def test_default_shape_follows_the_precision():
     assert comp["filter_slots"] % 6 == 0 and comp["filter_slots"] >= comp["total_filters"]
 
 
+def test_window_copies_follow_occupancy():
+    # delays up to 4095 samples: two window copies leave one 8-wave group per
+    # compute unit, one copy two; a bank of 4096 such templates has enough
+    # groups to use them, so the library keeps one copy ...
+    b2 = W.config2(n_templates=4096, n_blocks=1).bank
+    p2 = S.spiir_plan(b2, 2048)
+    assert p2["window_copies"] == 1
+    assert S.spiir_plan(b2, 2048, window_copies=2)["lds_bytes"] > p2["lds_bytes"]
+    # ... while 1024 of them make only one group per compute unit either way
+    assert S.spiir_plan(W.config2(n_templates=1024, n_blocks=1).bank, 2048)["window_copies"] == 2
+    # the multi-rate bank keeps the two-copy window (3 or more waves per SIMD)
+    b3 = W.config3(n_templates=8, n_blocks=1).bank
+    assert S.spiir_plan(b3, 4096)["window_copies"] == 2
+    assert S.spiir_plan(b3, 4096, precision="fp32_compensated")["window_copies"] == 2
+    assert S.spiir_plan(b3, 4096, window_copies=1)["window_copies"] == 1
+
+
 def test_long_delays_fall_back_to_a_smaller_launch_shape():
-    # a delay window of 16383 samples does not fit the LDS next to 8-wave reduction
-    # buffers; the default shape steps down instead of refusing the bank
+    # a two-copy delay window of 16383 samples does not fit the LDS next to
+    # 8-wave reduction buffers; the default shape keeps one copy, and with two
+    # copies asked for it steps down instead of refusing the bank
     tb = W.random_bank(21, np.array([[64], [64]], np.int32), 4096, [16383])
     tb.delay = tb.delay.copy()
     tb.delay[0] = 16383
     p = S.spiir_plan(tb, 4096)
-    assert p["lanes_per_group"] < 512 and p["lds_bytes"] <= 160 * 1024
-    with pytest.raises(S.SpiirError):
-        S.spiir_plan(tb, 4096, waves_per_group=8)  # an explicit shape is not changed
+    assert p["window_copies"] == 1 and p["lds_bytes"] <= 160 * 1024
+    p2 = S.spiir_plan(tb, 4096, window_copies=2)
+    assert p2["lanes_per_group"] < 512 and p2["lds_bytes"] <= 160 * 1024
+    with pytest.raises(S.SpiirError):  # an explicit shape is not changed
+        S.spiir_plan(tb, 4096, waves_per_group=8, window_copies=2)
     # ordinary delays keep the 8-wave default
     assert S.spiir_plan(W.config3(n_templates=8, n_blocks=1).bank, 4096)["lanes_per_group"] == 512

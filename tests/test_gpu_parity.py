@@ -282,9 +282,11 @@ def test_largest_delay_with_the_default_shape():
     tb.delay = tb.delay.copy()
     tb.delay[:4] = 16383
     x = W.noise_stream(22, 6 * 4096)
-    zg = run_gpu(tb, x, [4096] * 6)
     zr = oracle.run_stream(tb, x)
-    check(zg, zr, label="max-delay")
+    # the library's shape (one window copy) and the smaller groups two copies need
+    for wc in (0, 2):
+        zg = run_gpu(tb, x, [4096] * 6, window_copies=wc)
+        check(zg, zr, label=f"max-delay, window copies {wc or 'default'}")
 
 
 @pytest.mark.parametrize("F,Wv", [(1, 1), (2, 2), (4, 4), (8, 4), (8, 8), (4, 8), (1, 8), (6, 8), (6, 2)])
@@ -303,6 +305,23 @@ def test_carry_chunk_variants(C):
     zg = run_gpu(wl.bank, x, [4096], carry_chunk=C)
     zr = oracle.run_stream(wl.bank, x)
     check(zg, zr, label=f"C{C}")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_compensated"])
+def test_one_window_copy_gives_the_same_bits(precision):
+    """The single-copy input window (two 32-bit reads per sample pair) reads the same
+    samples as the two-copy one, so the output is identical; checked on a
+    multi-rate bank and a single-rate bank with long delays."""
+    tb_mr = _mr_bank(seed=61, T=5, H=4, rate=2048)
+    tb_sr = W.random_bank(62, np.array([[300], [41], [180]], np.int32), 2048, [4095])
+    x = W.noise_stream(63, 4 * 2048)
+    for tb in (tb_mr, tb_sr):
+        z1 = run_gpu(tb, x, [2048, 1000, 1048, 4096], max_block=4096, precision=precision,
+                     window_copies=1)
+        z2 = run_gpu(tb, x, [2048, 1000, 1048, 4096], max_block=4096, precision=precision,
+                     window_copies=2)
+        assert np.array_equal(z1, z2)
+        check(z1, oracle.run_stream(tb, x), label=f"one window copy ({precision})")
 
 
 def test_compensated_mode():
