@@ -227,6 +227,26 @@ def test_block_split_is_bitwise_invariant():
     assert np.array_equal(a, b)
 
 
+def test_output_rows_at_any_alignment():
+    """z rows whose start is not 16-byte aligned (odd row stride) take the 8-byte
+    store path of the up-add; the values are the same bits."""
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    tb = _mr_bank(seed=71, T=5, H=3)
+    x = W.noise_stream(72, 2048)
+    ref = run_gpu(tb, x, [1024, 1024], max_block=1024)
+    bank = S.Bank(tb, 1024)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    zbuf = torch.zeros((tb.n_templates, 2 * 1024 + 1), dtype=torch.complex64, device="cuda")
+    assert zbuf.stride(0) % 2 == 1
+    for b in range(2):
+        bank.process_block(xt[b * 1024:(b + 1) * 1024], zbuf[:, b * 1024:(b + 1) * 1024])
+    torch.cuda.synchronize()
+    got = zbuf[:, :2048].cpu().numpy().astype(np.complex128)
+    bank.destroy()
+    assert np.array_equal(got, ref)
+
+
 def test_ragged_blocks_and_tails():
     tb = _mr_bank(seed=4, T=3, H=3)
     x = W.noise_stream(6, 3000)
