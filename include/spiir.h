@@ -311,6 +311,10 @@ typedef struct {
 
 int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info);
 
+/* The same summary for a created bank (the plan spiir_create made, without
+ * planning again).  SPIIR_EINVAL for NULL arguments. */
+int spiir_bank_plan(const spiir_bank* bank, spiir_plan_info* info);
+
 /* Process-wide kernel timing with HIP events recorded around each kernel the
  * library launches.  spiir_profile_enable(1) clears and starts recording;
  * spiir_profile_read waits for the recorded events and returns, per kernel

@@ -771,17 +771,8 @@ const char* spiir_strerror(int status)
     }
 }
 
-int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info)
+static void fill_plan_info(const Plan& p, spiir_plan_info* info)
 {
-    if (!info) return SPIIR_EINVAL;
-    Plan p;
-    int rc;
-    try {
-        rc = make_plan(desc, p);
-    } catch (const std::bad_alloc&) {
-        return SPIIR_ENOMEM;
-    }
-    if (rc) return rc;
     info->total_filters = p.total_filters;
     info->filter_slots = p.n_slots;
     info->n_groups = (int32_t)p.wg.size();
@@ -793,6 +784,27 @@ int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info)
     info->footprint = p.footprint;
     info->time_chunks = p.P;
     info->window_copies = p.copies;
+}
+
+int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info)
+{
+    if (!info) return SPIIR_EINVAL;
+    Plan p;
+    int rc;
+    try {
+        rc = make_plan(desc, p);
+    } catch (const std::bad_alloc&) {
+        return SPIIR_ENOMEM;
+    }
+    if (rc) return rc;
+    fill_plan_info(p, info);
+    return SPIIR_OK;
+}
+
+int spiir_bank_plan(const spiir_bank* bank, spiir_plan_info* info)
+{
+    if (!bank || !info) return SPIIR_EINVAL;
+    fill_plan_info(bank->plan, info);
     return SPIIR_OK;
 }
 

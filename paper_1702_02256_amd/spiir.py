@@ -120,6 +120,7 @@ def load_library():
         "spiir_strerror": (C.c_char_p, [C.c_int]),
         "spiir_samples_done": (C.c_int, [vp, C.POINTER(C.c_int64)]),
         "spiir_plan": (C.c_int, [C.POINTER(BankDesc), C.POINTER(PlanInfo)]),
+        "spiir_bank_plan": (C.c_int, [vp, C.POINTER(PlanInfo)]),
         "spiir_profile_enable": (C.c_int, [C.c_int]),
         "spiir_profile_read": (C.c_int, [C.POINTER(ProfileData)]),
         "spiir_process_peaks": (C.c_int, [vp, vp, i64, vp, i64, vp, C.c_float, vp]),
@@ -332,13 +333,13 @@ class Bank:
         self.n_templates = int(tables.n_filters.shape[0])
         self.n_bands = int(tables.n_filters.shape[1])
         self.max_block = int(max_block)
-        self.plan = spiir_plan(tables, max_block, precision=precision, carry_chunk=carry_chunk,
-                               filters_per_lane=filters_per_lane, waves_per_group=waves_per_group,
-                               device=device, time_chunks=time_chunks, window_copies=window_copies)
         h = C.c_void_p()
         s = _stream_handle(stream) if stream is not None else C.c_void_p(0)
         _check(lib.spiir_create(C.byref(hold.desc), s, C.byref(h)), "spiir_create")
         self._h = h.value
+        info = PlanInfo()
+        _check(lib.spiir_bank_plan(self._h, C.byref(info)), "spiir_bank_plan")
+        self.plan = {k: getattr(info, k) for k, _ in PlanInfo._fields_}
 
     def process_block(self, x, z, stream=None) -> None:
         _validate_io(self, x, z)

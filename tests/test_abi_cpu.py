@@ -144,6 +144,8 @@ def test_process_calls_reject_null_bank():
     assert lib.spiir_graph_destroy(None) == S.SPIIR_OK
     assert lib.spiir_process_peaks(None, None, 16, None, 16, None, 0.0, None) == S.SPIIR_EINVAL
     assert lib.spiir_process_batch_peaks(0, None, None, 0.0, None) == S.SPIIR_EINVAL
+    info = S.PlanInfo()
+    assert lib.spiir_bank_plan(None, C.byref(info)) == S.SPIIR_EINVAL
 
 
 @pytest.mark.skipif(_have_gpu(), reason="checks the no-device error path")
