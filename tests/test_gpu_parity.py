@@ -287,6 +287,16 @@ def test_other_resampler_lengths(n_down, n_up):
     check(zg, zr, label=f"taps {n_down}/{n_up}")
 
 
+def test_bank_without_filters():
+    """A bank whose templates have no filters at all runs (no filter workgroups)
+    and outputs exact zeros; also split in time."""
+    tb = W.random_bank(81, np.zeros((3, 3), np.int32), 1024, W.multirate_dmax(1024, 3))
+    x = W.noise_stream(82, 2048)
+    for kw in ({}, {"time_chunks": 4}):
+        zg = run_gpu(tb, x, [1024, 1024], max_block=1024, **kw)
+        assert np.array_equal(zg, np.zeros_like(zg))
+
+
 def test_large_delays_use_subblocks():
     nf = np.array([[64], [64]], np.int32)
     tb = W.random_bank(13, nf, 4096, [12000])
