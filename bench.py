@@ -28,11 +28,17 @@ KERNEL_SOURCES = ("paper_1702_02256_amd/csrc/spiir_kernels.hip", "paper_1702_022
 
 
 def kernel_source_hash() -> str:
+    """sha1 of the kernel and planner sources with comments and blank space
+    removed, so that only changes to the code itself invalidate a profile."""
     import hashlib
+    import re
     h = hashlib.sha1()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(HERE, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -30,8 +30,9 @@ constexpr int kSlotNone = 0xffff;
 // filters a lane needs more than 128 VGPRs, so at most 2 waves per SIMD.
 constexpr int filter_max_threads(int F) { return F >= 8 ? 512 : 1024; }
 // Waves per SIMD the compiler must leave room for (caps VGPRs at 512 / n):
-// with 4 filters and the plain sum a lane fits in 96 VGPRs without spilling,
-// so 5 waves; the compensated sum needs more, so 4.
+// with 4 filters and the plain sum a lane fits in 96 VGPRs (spills only
+// outside the sample loop), so 5 waves; the compensated sum needs more, so 4.
+// With 6 filters, 4 (128 VGPRs; again no spills in the sample loop).
 constexpr int filter_min_waves(int F, bool comp) { return F == 4 ? (comp ? 4 : 5) : F == 6 ? 4 : 1; }
 
 struct alignas(8) c32 {
