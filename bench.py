@@ -347,7 +347,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(templates shard across GPUs with no exchange; run one process per GPU "
               "on its own bank instead)", file=sys.stderr, flush=True)
         sys.exit(2)
