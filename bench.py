@@ -339,7 +339,7 @@ def main():
                          "throughput for this bank")
     ap.add_argument("--graph", action="store_true",
                     help="record the block's launch sequence once and replay it per step")
-    ap.add_argument("--cpu-budget", type=float, default=2.0,
+    ap.add_argument("--cpu-budget", type=float, default=10.0,
                     help="wall seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
