@@ -319,7 +319,7 @@ def test_largest_delay_with_the_default_shape():
         check(zg, zr, label=f"max-delay, window copies {wc or 'default'}")
 
 
-@pytest.mark.parametrize("F,Wv", [(1, 1), (2, 2), (4, 4), (8, 4), (8, 8), (4, 8), (1, 8), (6, 8), (6, 2)])
+@pytest.mark.parametrize("F,Wv", [(1, 1), (2, 2), (4, 4), (8, 4), (8, 8), (4, 8), (1, 8), (6, 8), (6, 2), (6, 5)])
 def test_lane_packing_variants(F, Wv):
     tb = _mr_bank(seed=15, T=6, H=3, lo=1, hi=300)
     x = W.noise_stream(16, 2048)
