@@ -442,6 +442,17 @@ def test_mixed_batch_equals_alone_bitwise():
         banks[i].destroy()
 
 
+def test_created_bank_reports_the_planned_shape():
+    """spiir_bank_plan of a created bank equals spiir_plan of its descriptor."""
+    from paper_1702_02256_amd import spiir as S
+    tb = _mr_bank(seed=91, T=6, H=4, rate=2048)
+    for kw in ({}, {"precision": "fp32_compensated"}, {"window_copies": 1, "filters_per_lane": 2},
+               {"time_chunks": 4}):
+        bank = S.Bank(tb, 2048, **kw)
+        assert bank.plan == S.spiir_plan(tb, 2048, **kw), kw
+        bank.destroy()
+
+
 def test_save_load_roundtrip_bitwise():
     torch = _torch()
     from paper_1702_02256_amd import spiir as S
