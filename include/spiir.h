@@ -273,7 +273,10 @@ int spiir_state_size(const spiir_bank* bank, size_t* bytes);
 int spiir_save_state(spiir_bank* bank, void* host_buf, void* hip_stream);
 
 /* spiir_load_state — restore a blob from spiir_save_state of a bank with the
- * same shape (SPIIR_EINVAL if the header does not match).  Synchronous. */
+ * same shape and filter layout: the same sizes, launch shape and delays, as a
+ * bank created from the same descriptor has.  The blob's header carries a
+ * fingerprint of the layout; SPIIR_EINVAL (state unchanged) if the header does
+ * not match.  Synchronous. */
 int spiir_load_state(spiir_bank* bank, const void* host_buf, void* hip_stream);
 
 /* spiir_status — sticky non-finite flags.  Waits for the bank's work.

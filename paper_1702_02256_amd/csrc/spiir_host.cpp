@@ -32,7 +32,8 @@ constexpr int kXcapMax = 24576;     // LDS window, floats
 constexpr int kMaxLds = 160 * 1024;
 constexpr int kComputeUnits = 256;  // MI355X
 constexpr uint32_t kStateMagic = 0x53504952u;  // "SPIR"
-constexpr uint32_t kStateVersion = 2;  // 2: the carried chunk value is the pending correction
+constexpr uint32_t kStateVersion = 3;  // 3: 128-byte header with the layout fingerprint
+constexpr int64_t kStateHeaderBytes = 128;
 
 int default_filters_per_lane(const spiir_bank_desc* d)
 {
@@ -569,7 +570,7 @@ int zero_state(spiir_bank* b, hipStream_t s)
 
 int64_t state_bytes(const Plan& p)
 {
-    return 64 + p.n_slots * 2 * (int64_t)sizeof(c32) + p.ring_total * (int64_t)sizeof(float) +
+    return kStateHeaderBytes + p.n_slots * 2 * (int64_t)sizeof(c32) + p.ring_total * (int64_t)sizeof(float) +
            (int64_t)p.T * p.H * p.hu_len * (int64_t)sizeof(c32) + (int64_t)p.T * 4;
 }
 
@@ -578,7 +579,31 @@ struct StateHeader {
     int32_t T, H, F, L, C, precision;
     int64_t n_slots, ring_total, done;
     int64_t hist;
+    uint64_t layout;  // layout_fingerprint of the bank that wrote the blob
 };
+static_assert(sizeof(StateHeader) <= kStateHeaderBytes, "state header");
+
+// FNV-1a over what decides where each value of the state lives: the filter
+// behind every slot (its descriptor index and delay), the workgroup bands and
+// the input ring sizes.  Banks of equal sizes whose delays place their filters
+// differently get different fingerprints, so a blob cannot be loaded into them.
+uint64_t layout_fingerprint(const Plan& p)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* data, size_t bytes) {
+        const unsigned char* c = static_cast<const unsigned char*>(data);
+        for (size_t i = 0; i < bytes; ++i) {
+            h ^= c[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(p.slot_src.data(), p.slot_src.size() * sizeof(int64_t));
+    mix(p.slot_off.data(), p.slot_off.size() * sizeof(int32_t));
+    mix(p.band_wg0.data(), p.band_wg0.size() * sizeof(int));
+    mix(p.ring_mask.data(), p.ring_mask.size() * sizeof(int));
+    mix(&p.hu_len, sizeof(p.hu_len));
+    return h;
+}
 
 // peaks: the per-request trigger outputs (null for plain calls); with them a
 // request may leave z_dev null.
@@ -1094,11 +1119,12 @@ int spiir_save_state(spiir_bank* b, void* host_buf, void* stream)
     hipError_t e = hipSuccess;
     if (b->ev_recorded) e = hipStreamWaitEvent(s, b->ev, 0);
     StateHeader hdr{kStateMagic, kStateVersion, p.T, p.H, p.F, p.L, p.C, p.precision,
-                    p.n_slots, p.ring_total, b->done, (int64_t)p.T * p.H * p.hu_len};
+                    p.n_slots, p.ring_total, b->done, (int64_t)p.T * p.H * p.hu_len,
+                    layout_fingerprint(p)};
     char* o = (char*)host_buf;
-    std::memset(o, 0, 64);
+    std::memset(o, 0, kStateHeaderBytes);
     std::memcpy(o, &hdr, sizeof(hdr));
-    o += 64;
+    o += kStateHeaderBytes;
     auto dn = [&](const void* src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpyAsync(o, src, bytes, hipMemcpyDeviceToHost, s);
         o += bytes;
@@ -1125,12 +1151,13 @@ int spiir_load_state(spiir_bank* b, const void* host_buf, void* stream)
     std::memcpy(&hdr, host_buf, sizeof(hdr));
     if (hdr.magic != kStateMagic || hdr.version != kStateVersion || hdr.T != p.T || hdr.H != p.H ||
         hdr.F != p.F || hdr.L != p.L || hdr.C != p.C || hdr.n_slots != p.n_slots ||
-        hdr.ring_total != p.ring_total || hdr.hist != (int64_t)p.T * p.H * p.hu_len || hdr.done < 0)
+        hdr.ring_total != p.ring_total || hdr.hist != (int64_t)p.T * p.H * p.hu_len || hdr.done < 0 ||
+        hdr.done % (1 << (p.H - 1)) != 0 || hdr.layout != layout_fingerprint(p))
         return SPIIR_EINVAL;
     int rc = bank_sync(b);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const char* o = (const char*)host_buf + 64;
+    const char* o = (const char*)host_buf + kStateHeaderBytes;
     hipError_t e = hipSuccess;
     auto upl = [&](void* dst, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, o, bytes, hipMemcpyHostToDevice, s);

@@ -381,6 +381,9 @@ class Bank:
         return buf.raw
 
     def load_state(self, blob: bytes, stream=None) -> None:
+        # the library reads state_size() bytes: a blob of another length is refused here
+        if len(blob) != self.state_size():
+            raise SpiirError(SPIIR_EINVAL, "spiir_load_state")
         buf = C.create_string_buffer(bytes(blob), len(blob))
         _check(self._lib.spiir_load_state(self._h, buf, _stream_handle(stream)), "spiir_load_state")
 

@@ -480,6 +480,52 @@ def test_save_load_roundtrip_bitwise():
     bank.destroy()
 
 
+def test_state_blob_is_tied_to_the_filter_layout():
+    """A blob resumes a bank made from the same tables, and is refused by a bank
+    of equal sizes whose delays place the filters differently, or when its
+    header is damaged."""
+    import dataclasses
+    import struct
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    tb = _mr_bank(seed=42, T=3, H=3)
+    xt = torch.from_numpy(W.noise_stream(43, 4096).astype(np.float32)).cuda()
+    bank = S.Bank(tb, 2048)
+    z = torch.zeros((3, 2048), dtype=torch.complex64, device="cuda")
+    bank.process_block(xt[:2048], z)
+    blob = bank.save_state()
+    fresh = S.Bank(tb, 2048)
+    fresh.load_state(blob)
+    assert fresh.samples_done == 2048
+    z1, z2 = torch.zeros_like(z), torch.zeros_like(z)
+    bank.process_block(xt[2048:], z1)
+    fresh.process_block(xt[2048:], z2)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z2)
+    # the same delays reversed inside each (template, band) segment: equal sizes,
+    # another placement of the filters over lanes and slots
+    segs = np.cumsum(np.concatenate([[0], tb.n_filters.ravel()]))
+    d2 = np.concatenate([tb.delay[a:b][::-1] for a, b in zip(segs[:-1], segs[1:])]).astype(np.int32)
+    other = S.Bank(dataclasses.replace(tb, delay=d2), 2048)
+    assert other.state_size() == len(blob)
+    with pytest.raises(S.SpiirError) as ei:
+        other.load_state(blob)
+    assert ei.value.code == S.SPIIR_EINVAL
+    bad = bytearray(blob)
+    bad[0] ^= 1  # magic
+    with pytest.raises(S.SpiirError):
+        fresh.load_state(bytes(bad))
+    bad = bytearray(blob)
+    struct.pack_into("<q", bad, 48, 2049)  # sample count: not a multiple of 2^(H-1)
+    with pytest.raises(S.SpiirError):
+        fresh.load_state(bytes(bad))
+    with pytest.raises(S.SpiirError):  # a truncated blob
+        fresh.load_state(blob[:-4])
+    assert other.samples_done == 0 and fresh.samples_done == 4096
+    for b in (bank, fresh, other):
+        b.destroy()
+
+
 def test_invalid_block_leaves_state_unchanged():
     torch = _torch()
     from paper_1702_02256_amd import spiir as S
