@@ -287,6 +287,44 @@ def test_other_resampler_lengths(n_down, n_up):
     check(zg, zr, label=f"taps {n_down}/{n_up}")
 
 
+@pytest.mark.parametrize("taps", [32, 1024])
+def test_most_bands_and_longest_resamplers(taps):
+    """SPIIR_MAX_BANDS bands (the lowest one gets a single sample of a 2048-sample
+    block, fewer than the resampler histories hold); with SPIIR_MAX_TAPS taps the
+    up-add needs more than 64 KB of LDS."""
+    H = 12
+    nf = np.random.default_rng(17).integers(1, 20, size=(3, H)).astype(np.int32)
+    tb = W.random_bank(17, nf, 4096, W.multirate_dmax(4096, H), n_taps_down=taps, n_taps_up=taps)
+    x = W.noise_stream(18, 16384)
+    zg = run_gpu(tb, x, [2048, 4096, 8192, 2048], max_block=8192)
+    zr = oracle.run_stream(tb, x)
+    check(zg, zr, label=f"H=12 taps={taps}")
+
+
+def test_largest_batch():
+    """SPIIR_MAX_BATCH banks of different band counts in one batch, each result
+    the bank's own; one more request is refused before anything is enqueued."""
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    nb = S.MAX_BATCH
+    tabs = [_mr_bank(seed=100 + i, T=1 + i % 3, H=1 + i % 4, hi=40) for i in range(nb + 1)]
+    xs = [W.noise_stream(200 + i, 1024) for i in range(nb + 1)]
+    alone = [run_gpu(tabs[i], xs[i], [1024]) for i in range(nb)]
+    banks = [S.Bank(t, 1024) for t in tabs]
+    xt = [torch.from_numpy(x.astype(np.float32)).cuda() for x in xs]
+    zt = [torch.zeros((t.n_templates, 1024), dtype=torch.complex64, device="cuda") for t in tabs]
+    with pytest.raises(S.SpiirError) as ei:
+        S.spiir_process_batch([(banks[i], xt[i], zt[i]) for i in range(nb + 1)])
+    assert ei.value.code == S.SPIIR_EINVAL
+    assert all(b.samples_done == 0 for b in banks)
+    S.spiir_process_batch([(banks[i], xt[i], zt[i]) for i in range(nb)])
+    torch.cuda.synchronize()
+    for i in range(nb):
+        assert np.array_equal(zt[i].cpu().numpy().astype(np.complex128), alone[i]), i
+    for b in banks:
+        b.destroy()
+
+
 def test_bank_without_filters():
     """A bank whose templates have no filters at all runs (no filter workgroups)
     and outputs exact zeros; also split in time."""
