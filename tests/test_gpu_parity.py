@@ -366,6 +366,45 @@ def test_lane_packing_variants(F, Wv):
     check(zg, zr, label=f"F{F}W{Wv}")
 
 
+def _random_case(i):
+    """A seeded random bank, block sequence and launch shape (band count, rates,
+    filter counts with empty segments, delays up to one second, resampler
+    lengths, lanes, waves, carry chunk, time split, window layout, precision);
+    draws that the planner refuses (an explicit shape whose window does not fit
+    the LDS) are drawn again."""
+    from paper_1702_02256_amd import spiir as S
+    rng = np.random.default_rng([777, i])
+    while True:
+        H = int(rng.integers(1, 6))
+        rate = int(rng.choice([512, 1024, 2048]))
+        T = int(rng.integers(1, 7))
+        nf = rng.integers(0, 120, size=(T, H)) * (rng.random((T, H)) > 0.2)
+        dmax = [int(rng.integers(0, max(rate >> h, 2))) for h in range(H)]
+        tb = W.random_bank(int(rng.integers(1 << 30)), nf.astype(np.int32), rate, dmax,
+                           n_taps_down=int(rng.integers(1, 65)), n_taps_up=int(rng.integers(1, 65)))
+        unit = 1 << (H - 1)
+        max_block = unit * int(rng.integers(1, 8192 // unit + 1))
+        blocks = [unit * int(rng.integers(1, max_block // unit + 1)) for _ in range(int(rng.integers(2, 5)))]
+        kw = dict(filters_per_lane=int(rng.choice([1, 2, 4, 6, 8])), waves_per_group=int(rng.choice([1, 2, 3, 4, 5, 8])),
+                  carry_chunk=int(rng.choice([16, 32, 64, 128])), time_chunks=int(rng.choice([0, 0, 2, 4, 8])),
+                  window_copies=int(rng.choice([0, 1, 2])),
+                  precision=str(rng.choice(["fp32", "fp32_compensated"])))
+        try:
+            S.spiir_plan(tb, max_block, **kw)
+        except S.SpiirError:
+            continue
+        return tb, max_block, blocks, kw
+
+
+@pytest.mark.parametrize("i", range(16))
+def test_random_configurations_match_the_oracle(i):
+    tb, max_block, blocks, kw = _random_case(i)
+    x = W.noise_stream(900 + i, sum(blocks))
+    zg = run_gpu(tb, x, blocks, max_block=max_block, **kw)
+    zr = oracle.run_stream(tb, x)
+    check(zg, zr, label=f"random {i}: T={tb.n_templates} H={tb.n_filters.shape[1]} blocks={blocks} {kw}")
+
+
 @pytest.mark.parametrize("C", [16, 64, 256])
 def test_carry_chunk_variants(C):
     wl = W.config1()
