@@ -326,7 +326,8 @@ def main():
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--carry-chunk", type=int, default=0)
     ap.add_argument("--time-chunks", type=int, default=0,
-                    help="split every block in time into this many chunks (small banks)")
+                    help="split every block in time into this many chunks (small banks); "
+                         "-1: the library chooses")
     ap.add_argument("--window-copies", type=int, default=0, choices=[0, 1, 2],
                     help="LDS copies of the filter kernel's input window (0 = library choice)")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp32_compensated"],

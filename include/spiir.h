@@ -94,7 +94,14 @@ enum {
  *                         6 or more filters per lane; fewer when a long
  *                         delay window would not fit the LDS).
  *   device                HIP device ordinal the bank lives on.
- *   time_chunks           P in {0, 1, 2, 4, ..., 64}; 0 or 1 = off.  With
+ *   time_chunks           P in {0, 1, 2, 4, ..., 64}; 0 or 1 = off;
+ *                         SPIIR_TIME_CHUNKS_AUTO: the library picks P for
+ *                         blocks of max_block samples, splitting while the
+ *                         longest workgroup's run of dependent samples, cut
+ *                         in P, is no shorter than the bank's filter work
+ *                         per workgroup slot of the device (spiir_plan
+ *                         reports the choice; P = 1 for banks that fill the
+ *                         device, up to 64 for a single small template).  With
  *                         P > 1 each block is also split in time, so banks
  *                         too small to fill the device finish sooner: every
  *                         band's samples are cut at absolute multiples of a
@@ -140,6 +147,7 @@ typedef struct {
 #define SPIIR_MAX_DELAY 16383
 #define SPIIR_MAX_TAPS 1024
 #define SPIIR_MAX_BATCH 16
+#define SPIIR_TIME_CHUNKS_AUTO (-1)
 
 /* One request of a batch: the next n samples of the stream bound to `bank`. */
 typedef struct {

@@ -95,7 +95,8 @@ int validate(const spiir_bank_desc* d)
     const int W = d->waves_per_group ? d->waves_per_group : default_waves_per_group(F);
     if (W < 1 || 64 * W > filter_max_threads(F)) return SPIIR_EINVAL;
     if (d->device < 0) return SPIIR_EINVAL;
-    if (d->time_chunks < 0 || d->time_chunks > 64 || (d->time_chunks & (d->time_chunks - 1)) != 0)
+    if (d->time_chunks != SPIIR_TIME_CHUNKS_AUTO &&
+        (d->time_chunks < 0 || d->time_chunks > 64 || (d->time_chunks & (d->time_chunks - 1)) != 0))
         return SPIIR_EINVAL;
     if (d->window_copies < 0 || d->window_copies > 2) return SPIIR_EINVAL;
     int64_t total = 0;
@@ -434,7 +435,7 @@ int fit_shape(const spiir_bank_desc* d, Plan& p, int W, int copies)
 // bank's waves where two leave it fewer than 3 per SIMD (long delay windows
 // in banks large enough to fill the device); a copy less costs about 4% in
 // LDS reads, more waves per SIMD gain more.
-int make_plan(const spiir_bank_desc* d, Plan& p)
+int make_plan_fixed(const spiir_bank_desc* d, Plan& p)
 {
     int rc = validate(d);
     if (rc) return rc;
@@ -466,6 +467,52 @@ int make_plan(const spiir_bank_desc* d, Plan& p)
         return SPIIR_OK;
     }
     return SPIIR_EINVAL;
+}
+
+// Chunks for SPIIR_TIME_CHUNKS_AUTO.  A workgroup runs its band's samples of a
+// block one after the other; the split cuts that sequence into about P pieces
+// at the cost of an end-state pass.  It pays while the longest workgroup's
+// sequence, cut in P, stays at least as long as the bank's work per workgroup
+// slot of the device (work: the sum of every workgroup's band samples per
+// block; slots: groups per compute unit times compute units).  Measured with
+// the default shapes: single-rate banks of 64, 256 and 1024 templates of 512
+// filters take P = 16, 4 and 1, the best of the powers of two tried; the
+// multi-rate bank of 128, 512, 1024 and 4096 templates takes 16, 4, 2 and 1
+// (also the best tried).
+int auto_time_chunks(const Plan& p)
+{
+    int64_t work = 0;
+    int64_t longest = 0;
+    for (const WgDesc& w : p.wg) {
+        const int64_t nh = std::max(p.mb_inner >> w.band, 1);
+        work += nh;
+        longest = std::max(longest, nh);
+    }
+    if (work == 0) return 1;
+    const int by_lds = kMaxLds / std::max(p.lds_filter, 1);
+    const int by_regs = 4 * filter_reg_waves(p.F, p.precision == SPIIR_FP32_COMPENSATED) / p.W;
+    const int64_t slots = (int64_t)kComputeUnits * std::max(1, std::min(by_lds, by_regs));
+    int P = 1;
+    while (P < 64 && longest * slots >= 2 * P * work) P *= 2;
+    return P;
+}
+
+// The plan for a descriptor; an automatic time split plans the default (or
+// given) shape first, then the same shape split in time.
+int make_plan(const spiir_bank_desc* d, Plan& p)
+{
+    if (!d || d->time_chunks != SPIIR_TIME_CHUNKS_AUTO) return make_plan_fixed(d, p);
+    spiir_bank_desc d1 = *d;
+    d1.time_chunks = 0;
+    int rc = make_plan_fixed(&d1, p);
+    if (rc) return rc;
+    const int P = auto_time_chunks(p);
+    if (P < 2) return SPIIR_OK;
+    d1.time_chunks = P;
+    d1.filters_per_lane = p.F;
+    d1.waves_per_group = p.W;
+    d1.window_copies = p.copies;
+    return make_plan_fixed(&d1, p);
 }
 
 // ---------------------------------------------------------------- profiling

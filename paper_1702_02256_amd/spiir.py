@@ -27,6 +27,7 @@ SPIIR_ENONFINITE = -5
 SPIIR_FP32 = 0
 SPIIR_FP32_COMPENSATED = 1
 MAX_BATCH = 16
+TIME_CHUNKS_AUTO = -1  # time_chunks: the library chooses the split
 
 _PRECISION = {"fp32": SPIIR_FP32, "fp32_compensated": SPIIR_FP32_COMPENSATED,
               "compensated": SPIIR_FP32_COMPENSATED}

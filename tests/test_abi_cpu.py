@@ -94,7 +94,7 @@ def test_footprint_matches_plan_and_scales():
     ("n_bands", 0), ("n_bands", 13), ("max_block", 0), ("max_block", 1023 + 2),
     ("precision", 7), ("carry_chunk", 48), ("carry_chunk", 8), ("filters_per_lane", 3), ("window_copies", 3),
     ("waves_per_group", 17), ("base_rate_hz", 0), ("n_templates", 0), ("device", -1),
-    ("time_chunks", 3), ("time_chunks", 128), ("time_chunks", -1),
+    ("time_chunks", 3), ("time_chunks", 128), ("time_chunks", -2),
 ])
 def test_descriptor_validation(field, value):
     tb = _small_multirate()
@@ -165,6 +165,25 @@ def test_plan_time_chunks():
     # chunk states and the a1^length table are allocated only for a split bank
     assert p32["footprint"] > p1["footprint"]
     assert S.spiir_plan(wl.bank, 4096, time_chunks=1)["footprint"] == p1["footprint"]
+
+
+def test_automatic_time_split_follows_the_bank_size():
+    # the split pays while the longest workgroup's samples, cut in P, are no
+    # fewer than the bank's work per workgroup slot of the device
+    auto = S.TIME_CHUNKS_AUTO
+    assert S.spiir_plan(W.config1().bank, 4096, time_chunks=auto)["time_chunks"] == 64
+    sizes = {64: 16, 256: 4, 1024: 1}  # single-rate templates of 512 filters -> P
+    for T, P in sizes.items():
+        bank = W.config2(n_templates=T, n_blocks=1).bank
+        p = S.spiir_plan(bank, 2048, time_chunks=auto)
+        assert p["time_chunks"] == P, (T, p["time_chunks"])
+        assert p == S.spiir_plan(bank, 2048, time_chunks=P)
+    # an explicit shape is kept and split; a bank without filters is not split
+    p = S.spiir_plan(W.config2(n_templates=64, n_blocks=1).bank, 2048, time_chunks=auto,
+                     filters_per_lane=2, waves_per_group=2)
+    assert (p["filters_per_lane"], p["lanes_per_group"]) == (2, 128) and p["time_chunks"] > 1
+    empty = W.random_bank(5, np.zeros((2, 3), np.int32), 1024, W.multirate_dmax(1024, 3))
+    assert S.spiir_plan(empty, 1024, time_chunks=auto)["time_chunks"] == 1
 
 
 def test_default_shape_follows_the_precision():

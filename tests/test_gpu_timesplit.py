@@ -56,6 +56,25 @@ def test_single_rate_split_vs_oracle(P, F):
     assert e.max() <= TOL
 
 
+def test_automatic_split_equals_the_chosen_split():
+    """time_chunks = SPIIR_TIME_CHUNKS_AUTO plans a split for a small multi-rate
+    bank; the bank runs exactly as one created with that split given."""
+    from paper_1702_02256_amd import spiir as S
+    wl = W.config3(n_templates=12, n_blocks=1)
+    blocks = [4096, 1024, 3072]
+    x = W.noise_stream(4343, sum(blocks))
+    plan = S.spiir_plan(wl.bank, 4096, time_chunks=S.TIME_CHUNKS_AUTO)
+    P = plan["time_chunks"]
+    _say(f"automatic split: P={P}, {plan['n_groups']} groups")
+    assert P > 1
+    za = _run(wl.bank, x, blocks, 4096, time_chunks=S.TIME_CHUNKS_AUTO)
+    zp = _run(wl.bank, x, blocks, 4096, time_chunks=P)
+    assert np.array_equal(za.view(np.uint64), zp.view(np.uint64))
+    e = _rel_err(za.astype(np.complex128), oracle.run_stream(wl.bank, x))
+    _say(f"  max rel err {e.max():.3e}")
+    assert e.max() <= TOL
+
+
 def test_multirate_split_vs_oracle_and_long_blocks():
     wl = W.config3(n_templates=6, n_blocks=1)
     blocks = [4096, 8192, 1024, 2048 + 64]
