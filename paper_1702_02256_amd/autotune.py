@@ -1,8 +1,9 @@
 """Autotuner for the filter-bank launch shape and the serving block length.
 
 ``tune_packing`` times every valid (filters_per_lane F, waves_per_group W)
-candidate on the device for a bank shape (for banks too small to fill the
-device, also with the block split in time) and keeps the fastest; results are
+candidate on the device for a bank shape, each also with the time split the
+library's planner picks for it when that is a split (and, for banks too small
+to fill the device, a few fixed splits), and keeps the fastest; results are
 cached in a JSON file keyed by the GPU architecture and a signature of the
 bank shape (filters per band, largest delay per band, templates, block).
 ``tune_block`` picks the shortest block length whose throughput reaches a
@@ -100,8 +101,17 @@ def tune_packing(tables, block: int, candidates=None, steps: int = 3, use_cache:
     results = []
     if candidates is None:
         candidates = list(DEFAULT_CANDIDATES)
+        # each default shape also with the split the planner picks for it
+        for F, Wv in DEFAULT_CANDIDATES:
+            try:
+                P = S.spiir_plan(tables, block, **dict(bank_kw, filters_per_lane=F, waves_per_group=Wv,
+                                                       time_chunks=S.TIME_CHUNKS_AUTO))["time_chunks"]
+            except S.SpiirError:
+                continue
+            if P > 1:
+                candidates.append((F, Wv, P))
         if tables.total_filters / 4 < SMALL_BANK_LANES:
-            candidates += SMALL_BANK_CANDIDATES
+            candidates += [c for c in SMALL_BANK_CANDIDATES if c not in candidates]
     for cand in candidates:
         F, Wv = cand[0], cand[1]
         P = cand[2] if len(cand) > 2 else 1

@@ -19,8 +19,13 @@ def test_tune_packing_and_block(tmp_path, monkeypatch):
     assert not t["cached"] and len(t["candidates"]) >= 3
     tried = {(c["filters_per_lane"], c["waves_per_group"], c["time_chunks"]) for c in t["candidates"]}
     assert (t["filters_per_lane"], t["waves_per_group"], t["time_chunks"]) in tried
-    # a bank this small also gets the time-split candidates
+    # a bank this small also gets the time-split candidates, among them the
+    # split the planner picks for each default shape
     assert any(c[2] > 1 for c in tried)
+    for F, Wv in A.DEFAULT_CANDIDATES:
+        P = S.spiir_plan(tb, 1024, filters_per_lane=F, waves_per_group=Wv,
+                         time_chunks=S.TIME_CHUNKS_AUTO)["time_chunks"]
+        assert P == 1 or (F, Wv, P) in tried, (F, Wv, P)
     assert A.tune_packing(tb, 1024)["cached"]
     b = A.tune_block(tb, blocks=(256, 1024, 4096), steps=2)
     assert b["block"] in (256, 1024, 4096)
