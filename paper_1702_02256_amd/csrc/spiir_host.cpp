@@ -435,7 +435,7 @@ int fit_shape(const spiir_bank_desc* d, Plan& p, int W, int copies)
 // bank's waves where two leave it fewer than 3 per SIMD (long delay windows
 // in banks large enough to fill the device); a copy less costs about 4% in
 // LDS reads, more waves per SIMD gain more.
-int make_plan_fixed(const spiir_bank_desc* d, Plan& p)
+int make_plan_shaped(const spiir_bank_desc* d, Plan& p, int w_cap)
 {
     int rc = validate(d);
     if (rc) return rc;
@@ -445,7 +445,7 @@ int make_plan_fixed(const spiir_bank_desc* d, Plan& p)
         ws.push_back(d->waves_per_group);
     else
         for (int w : {8, 4, 2, 1})
-            if (w <= default_waves_per_group(F) && 64 * w <= filter_max_threads(F)) ws.push_back(w);
+            if (w <= w_cap && 64 * w <= filter_max_threads(F)) ws.push_back(w);
     for (int w : ws) {
         if (d->window_copies) {
             rc = fit_shape(d, p, w, d->window_copies);
@@ -467,6 +467,49 @@ int make_plan_fixed(const spiir_bank_desc* d, Plan& p)
         return SPIIR_OK;
     }
     return SPIIR_EINVAL;
+}
+
+// Rounds of workgroups the device runs for this plan: workgroups over
+// workgroup slots (what the LDS and registers allow per compute unit, times
+// the compute units).
+double group_rounds(const Plan& p)
+{
+    const int by_lds = kMaxLds / std::max(p.lds_filter, 1);
+    const int by_regs = 4 * filter_reg_waves(p.F, p.precision == SPIIR_FP32_COMPENSATED) / p.W;
+    return (double)p.wg.size() / ((double)kComputeUnits * std::max(1, std::min(by_lds, by_regs)));
+}
+
+// The default launch shape (no filters_per_lane and no waves_per_group given).
+// The shapes that run a full bank fastest (F = 6, W = 4 compensated; F = 4,
+// W = 8 plain) have large workgroups.  A bank that does not fill the device
+// with them, or a multi-rate bank with only a few rounds of them (its band-0
+// workgroups, the longest, then decide when the block ends), runs faster in
+// workgroups of 4 waves with 4 filters per lane: more, smaller workgroups
+// balance better.  Measured, ms per block (large shape -> F = 4, W = 4):
+// compensated, config-3 banks of 1024, 2048, 3072, 4096 templates (1.1, 2.1,
+// 3.2, 4.3 rounds) 0.80 -> 0.66, 0.98 -> 0.86, 1.03 -> 1.10, 1.34 -> 1.45;
+// the uneven bank of 8192 templates (1.9 rounds) 1.42 -> 1.31; the single-rate
+// bank of 1024 x 512 filters (0.7 rounds) 0.47 -> 0.38.  Plain: config-3 banks
+// of 1024, 2048, 3072, 4096 templates (1.2, 2.4, 3.6, 4.8 rounds) 0.71 -> 0.61,
+// 0.93 -> 0.79, 1.19 -> 1.05, 1.32 -> 1.38; the uneven bank (2.0 rounds) 1.31
+// -> 1.21; the single-rate bank (1.0 round) 0.348 -> 0.355.
+int make_plan_fixed(const spiir_bank_desc* d, Plan& p)
+{
+    if (!d) return SPIIR_EINVAL;
+    const int F = default_filters_per_lane(d);
+    int rc = make_plan_shaped(d, p, default_waves_per_group(F));
+    if (rc || d->filters_per_lane || d->waves_per_group) return rc;
+    int bands_used = 0;
+    for (int h = 0; h < p.H; ++h) bands_used += p.band_wg0[h + 1] > p.band_wg0[h];
+    const double rounds = group_rounds(p);
+    const double keep = bands_used > 1 ? (p.precision == SPIIR_FP32_COMPENSATED ? 3.0 : 4.0) : 1.0;
+    if (rounds >= keep || (p.F == 4 && p.W <= 4)) return SPIIR_OK;
+    spiir_bank_desc d4 = *d;
+    d4.filters_per_lane = 4;
+    Plan small;
+    if (make_plan_shaped(&d4, small, 4) != SPIIR_OK) return SPIIR_OK;
+    p = std::move(small);
+    return SPIIR_OK;
 }
 
 // Chunks for SPIIR_TIME_CHUNKS_AUTO.  A workgroup runs its band's samples of a

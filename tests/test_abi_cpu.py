@@ -186,18 +186,32 @@ def test_automatic_time_split_follows_the_bank_size():
     assert S.spiir_plan(empty, 1024, time_chunks=auto)["time_chunks"] == 1
 
 
-def test_default_shape_follows_the_precision():
-    bank = W.config3(n_templates=8, n_blocks=1).bank
-    plain = S.spiir_plan(bank, 4096)
-    comp = S.spiir_plan(bank, 4096, precision="fp32_compensated")
+def test_default_shape_follows_the_precision_and_the_bank_size():
+    # a full multi-rate bank: the large workgroups (6 filters per lane with the
+    # compensated sum, 8 waves with the plain one)
+    big = W.config3(n_blocks=1).bank
+    plain = S.spiir_plan(big, 4096)
+    comp = S.spiir_plan(big, 4096, precision="fp32_compensated")
     assert (plain["filters_per_lane"], plain["lanes_per_group"]) == (4, 512)
     assert (comp["filters_per_lane"], comp["lanes_per_group"]) == (6, 256)
-    # an explicit F keeps its own default width; explicit shapes are kept
-    assert S.spiir_plan(bank, 4096, filters_per_lane=8)["lanes_per_group"] == 256
-    assert S.spiir_plan(bank, 4096, precision="fp32_compensated", filters_per_lane=4,
-                        waves_per_group=8)["lanes_per_group"] == 512
     # every filter slot is a filter or padding: F = 6 packs segments in lanes of 6
     assert comp["filter_slots"] % 6 == 0 and comp["filter_slots"] >= comp["total_filters"]
+    # a multi-rate bank with few rounds of them takes 4 filters per lane in
+    # 4-wave groups; a single-rate bank only when it does not fill the device
+    small = W.config3(n_templates=1024, n_blocks=1).bank
+    for prec in ("fp32", "fp32_compensated"):
+        p = S.spiir_plan(small, 4096, precision=prec)
+        assert (p["filters_per_lane"], p["lanes_per_group"]) == (4, 256), prec
+    single = W.config2(n_blocks=1).bank
+    assert S.spiir_plan(single, 2048)["lanes_per_group"] == 512
+    p = S.spiir_plan(single, 2048, precision="fp32_compensated")
+    assert (p["filters_per_lane"], p["lanes_per_group"]) == (4, 256)
+    # an explicit F keeps its own default width; explicit shapes are kept
+    bank = W.config3(n_templates=8, n_blocks=1).bank
+    assert S.spiir_plan(bank, 4096, filters_per_lane=8)["lanes_per_group"] == 256
+    assert S.spiir_plan(bank, 4096, filters_per_lane=4)["lanes_per_group"] == 512
+    assert S.spiir_plan(bank, 4096, precision="fp32_compensated", filters_per_lane=4,
+                        waves_per_group=8)["lanes_per_group"] == 512
 
 
 def test_window_copies_follow_occupancy():
@@ -219,16 +233,17 @@ def test_window_copies_follow_occupancy():
 
 def test_long_delays_fall_back_to_a_smaller_launch_shape():
     # a two-copy delay window of 16383 samples does not fit the LDS next to
-    # 8-wave reduction buffers; the default shape keeps one copy, and with two
-    # copies asked for it steps down instead of refusing the bank
+    # 8-wave reduction buffers; 8-wave groups keep one copy, and with two
+    # copies asked for the shape steps down instead of refusing the bank
     tb = W.random_bank(21, np.array([[64], [64]], np.int32), 4096, [16383])
     tb.delay = tb.delay.copy()
     tb.delay[0] = 16383
-    p = S.spiir_plan(tb, 4096)
-    assert p["window_copies"] == 1 and p["lds_bytes"] <= 160 * 1024
-    p2 = S.spiir_plan(tb, 4096, window_copies=2)
+    assert S.spiir_plan(tb, 4096)["lds_bytes"] <= 160 * 1024
+    p = S.spiir_plan(tb, 4096, filters_per_lane=4)
+    assert p["window_copies"] == 1 and p["lanes_per_group"] == 512 and p["lds_bytes"] <= 160 * 1024
+    p2 = S.spiir_plan(tb, 4096, filters_per_lane=4, window_copies=2)
     assert p2["lanes_per_group"] < 512 and p2["lds_bytes"] <= 160 * 1024
     with pytest.raises(S.SpiirError):  # an explicit shape is not changed
         S.spiir_plan(tb, 4096, waves_per_group=8, window_copies=2)
     # ordinary delays keep the 8-wave default
-    assert S.spiir_plan(W.config3(n_templates=8, n_blocks=1).bank, 4096)["lanes_per_group"] == 512
+    assert S.spiir_plan(W.config3(n_templates=8, n_blocks=1).bank, 4096, filters_per_lane=4)["lanes_per_group"] == 512
