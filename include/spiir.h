@@ -197,9 +197,11 @@ int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c
  * spiir_process_batch — one launch sequence over up to SPIIR_MAX_BATCH
  * requests of different banks (each bank at most once: SPIIR_EORDER
  * otherwise; concatenate consecutive blocks of one stream instead).  Banks in
- * one batch must share device, filters_per_lane, waves_per_group and
- * precision (SPIIR_EINVAL otherwise).  Every result equals what separate
- * spiir_process_block calls give, bit for bit.  Validation is all-or-nothing.
+ * one batch must share the device (SPIIR_EINVAL otherwise); banks of
+ * different launch shapes (filters per lane, lanes per group, precision) get
+ * one filter launch per shape between the shared staging and up-add
+ * launches.  Every result equals what separate spiir_process_block calls
+ * give, bit for bit.  Validation is all-or-nothing.
  */
 int spiir_process_batch(int32_t n_req, const spiir_request* req, void* hip_stream);
 

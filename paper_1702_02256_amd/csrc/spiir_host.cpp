@@ -709,10 +709,7 @@ int validate_batch(int32_t n_req, const spiir_request* req, spiir_peak* const* p
         if (!q.x_dev) return SPIIR_EINVAL;
         if (peaks && !peaks[r]) return SPIIR_EINVAL;
         if (q.z_dev ? q.ldz < q.n : !peaks) return SPIIR_EINVAL;
-        const Plan& p0 = req[0].bank->plan;
-        if (q.bank->device != req[0].bank->device || p.F != p0.F || p.L != p0.L ||
-            p.precision != p0.precision)
-            return SPIIR_EINVAL;
+        if (q.bank->device != req[0].bank->device) return SPIIR_EINVAL;
         for (int s = 0; s < r; ++s)
             if (req[s].bank == q.bank) return SPIIR_EORDER;
     }
@@ -738,12 +735,11 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
     hipError_t e = hipSuccess;
     int64_t maxn = 0;
     for (int r = 0; r < n_req; ++r) maxn = std::max<int64_t>(maxn, req[r].n);
-    const int F = req[0].bank->plan.F, L = req[0].bank->plan.L, prec = req[0].bank->plan.precision;
     for (int64_t c0 = 0; c0 < maxn && e == hipSuccess; c0 += kInnerBlock) {
         LaunchArgs A;
         std::memset(&A, 0, sizeof(A));
         int rmap[SPIIR_MAX_BATCH];
-        int lds_f = 0, lds_s = 0, lds_u = 0, nwg = 0, ntm = 0, maxH = 0;
+        int lds_s = 0, lds_u = 0, ntm = 0, maxH = 0;
         for (int r = 0; r < n_req; ++r) {
             const spiir_request& q = req[r];
             if (q.n <= c0) continue;
@@ -762,21 +758,37 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
             ra.c0 = (int32_t)c0;
             ra.thr2 = thr2;
             ra.nchunk = p.P > 1 ? p.P + 1 : 1;
-            lds_f = std::max(lds_f, p.lds_filter);
             lds_s = std::max(lds_s, p.lds_stage);
             lds_u = std::max(lds_u, p.lds_up);
             maxH = std::max(maxH, p.H);
         }
-        // filter workgroups: band-major across requests (longest bands first),
-        // chunk-major inside a (band, request) segment when split in time
-        auto segments = [&](LaunchArgs& X, bool split_only) {
+        // one filter launch per launch shape (filters per lane, lanes, precision)
+        // among the requests, in order of first appearance
+        struct Shape {
+            int F, L, prec;
+        };
+        std::vector<Shape> shapes;
+        auto shape_of = [&](int k) {
+            const Plan& p = req[rmap[k]].bank->plan;
+            return Shape{p.F, p.L, p.precision};
+        };
+        auto same = [](const Shape& a, const Shape& b) { return a.F == b.F && a.L == b.L && a.prec == b.prec; };
+        for (int k = 0; k < A.nreq; ++k) {
+            bool seen = false;
+            for (const Shape& sh : shapes) seen |= same(sh, shape_of(k));
+            if (!seen) shapes.push_back(shape_of(k));
+        }
+        // filter workgroups of one shape: band-major across requests (longest
+        // bands first), chunk-major inside a (band, request) segment when split
+        // in time
+        auto segments = [&](LaunchArgs& X, bool split_only, const Shape& sh) {
             int total = 0;
             X.nseg = 0;
             X.cum[0] = 0;
             for (int h = 0; h < maxH; ++h)
                 for (int k = 0; k < X.nreq; ++k) {
                     const Plan& p = req[rmap[k]].bank->plan;  // X keeps A's request order
-                    if (h >= p.H) continue;
+                    if (h >= p.H || !same(shape_of(k), sh)) continue;
                     if (split_only && X.req[k].nchunk == 1) continue;
                     const int cnt = (p.band_wg0[h + 1] - p.band_wg0[h]) * X.req[k].nchunk;
                     if (cnt == 0) continue;
@@ -788,21 +800,16 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
                 }
             return total;
         };
-        nwg = segments(A, false);
-        // time split: end-state pass (A1) and chain pass (A2) over the split requests
-        LaunchArgs A1, A2;
-        int nwg1 = 0, lds_1 = 0;
+        // time split: end-state passes and one chain pass (A2) over the split requests
+        LaunchArgs A2;
         int64_t nchain = 0;
         bool split = false;
         for (int k = 0; k < A.nreq; ++k) split |= A.req[k].nchunk > 1;
         if (split) {
-            A1 = A;
-            nwg1 = segments(A1, true);
             std::memset(&A2, 0, sizeof(A2));
             for (int k = 0; k < A.nreq; ++k) {
                 if (A.req[k].nchunk == 1) continue;
                 const Plan& p = req[rmap[k]].bank->plan;
-                lds_1 = std::max(lds_1, p.lds_filter);
                 A2.req[A2.nreq] = A.req[k];
                 A2.cum[A2.nreq + 1] = A2.cum[A2.nreq] + (int32_t)((p.n_slots + 255) / 256);
                 A2.nreq++;
@@ -823,13 +830,31 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
             ev[i] = prof_event();
             if (ev[i]) (void)hipEventRecord(ev[i], s);
         };
+        // the LDS a shape's filter launch needs: the largest of its requests
+        auto shape_lds = [&](const Shape& sh, bool split_only) {
+            int lds = 0;
+            for (int k = 0; k < A.nreq; ++k)
+                if (same(shape_of(k), sh) && (!split_only || A.req[k].nchunk > 1))
+                    lds = std::max(lds, req[rmap[k]].bank->plan.lds_filter);
+            return lds;
+        };
         mark(0);
         e = (hipError_t)launch_stage(A, lds_s, s);
         mark(1);
-        if (e == hipSuccess && split && nwg1 > 0)
-            e = (hipError_t)launch_filter_local(F, prec, A1, nwg1, L, lds_1, s);
+        if (split)
+            for (const Shape& sh : shapes) {
+                LaunchArgs X = A;
+                const int n1 = segments(X, true, sh);
+                if (e == hipSuccess && n1 > 0)
+                    e = (hipError_t)launch_filter_local(sh.F, sh.prec, X, n1, sh.L, shape_lds(sh, true), s);
+            }
         if (e == hipSuccess && split && nchain > 0) e = (hipError_t)launch_chain(A2, nchain, s);
-        if (e == hipSuccess && nwg > 0) e = (hipError_t)launch_filter(F, prec, A, nwg, L, lds_f, s);
+        for (const Shape& sh : shapes) {
+            LaunchArgs X = A;
+            const int n0 = segments(X, false, sh);
+            if (e == hipSuccess && n0 > 0)
+                e = (hipError_t)launch_filter(sh.F, sh.prec, X, n0, sh.L, shape_lds(sh, false), s);
+        }
         mark(2);
         if (e == hipSuccess) e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
         mark(3);

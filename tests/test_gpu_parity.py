@@ -519,6 +519,43 @@ def test_mixed_batch_equals_alone_bitwise():
         banks[i].destroy()
 
 
+def test_batch_of_different_launch_shapes_equals_alone_bitwise():
+    """Banks of different lanes per filter, group sizes, precisions and time
+    splits in one batch (one filter launch per shape), eager and replayed from
+    a recording; each result is the bank's own, bit for bit."""
+    torch = _torch()
+    from paper_1702_02256_amd import spiir as S
+    shapes = [dict(filters_per_lane=6, waves_per_group=4, precision="fp32_compensated"), {},
+              dict(filters_per_lane=8, waves_per_group=2, time_chunks=4),
+              dict(filters_per_lane=1, waves_per_group=1, precision="fp32_compensated"),
+              dict(filters_per_lane=4, waves_per_group=8)]
+    tabs = [_mr_bank(seed=70 + i, T=2 + i, H=1 + i % 3) for i in range(len(shapes))]
+    xs = [W.noise_stream(80 + i, 2048) for i in range(len(shapes))]
+    alone = [run_gpu(tabs[i], xs[i], [1024, 1024], max_block=1024, **shapes[i]) for i in range(len(shapes))]
+    for graph in (False, True):
+        banks = [S.Bank(t, 1024, **kw) for t, kw in zip(tabs, shapes)]
+        assert len({(b.plan["filters_per_lane"], b.plan["lanes_per_group"]) for b in banks}) >= 4
+        xt = [torch.from_numpy(x.astype(np.float32)).cuda() for x in xs]
+        xb = [torch.empty(1024, device="cuda") for _ in xs]
+        zt = [torch.zeros((t.n_templates, 1024), dtype=torch.complex64, device="cuda") for t in tabs]
+        g = S.Graph([(banks[i], xb[i], zt[i]) for i in range(len(banks))]) if graph else None
+        for blk in range(2):
+            for i in range(len(banks)):
+                xb[i].copy_(xt[i][blk * 1024:(blk + 1) * 1024])
+            if g:
+                g.launch()
+            else:
+                S.spiir_process_batch([(banks[i], xb[i], zt[i]) for i in range(len(banks))])
+            torch.cuda.synchronize()
+            for i in range(len(banks)):
+                got = zt[i].cpu().numpy().astype(np.complex128)
+                assert np.array_equal(got, alone[i][:, blk * 1024:(blk + 1) * 1024]), (graph, blk, i)
+        if g:
+            g.destroy()
+        for b in banks:
+            b.destroy()
+
+
 def test_created_bank_reports_the_planned_shape():
     """spiir_bank_plan of a created bank equals spiir_plan of its descriptor."""
     from paper_1702_02256_amd import spiir as S
