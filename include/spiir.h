@@ -87,12 +87,18 @@ enum {
  *                         state is corrected by (a1^C - fl32(a1)^C) times the
  *                         state at the chunk start, computed in FP64 at
  *                         create; a power of two in [16, 1024]; 0 = 32.
- *   filters_per_lane      F in {1, 2, 4, 6, 8}; 0 = library default (4 with
- *                         the plain sum, 6 with the compensated sum).
+ *   filters_per_lane      F in {1, 2, 4, 6, 8}; 0 = library default.  With
+ *                         both this and waves_per_group 0 the library takes
+ *                         F = 4 with 8 waves (plain sum) or F = 6 with 4
+ *                         waves (compensated sum) for banks that fill the
+ *                         device with such workgroups (multi-rate banks:
+ *                         with at least 4 or 3 rounds of them), and F = 4
+ *                         with 4 waves otherwise.
  *   waves_per_group       wave64s per workgroup in [1, 16] ([1, 8] when
- *                         filters_per_lane is 8); 0 = default (8, or 4 with
- *                         6 or more filters per lane; fewer when a long
- *                         delay window would not fit the LDS).
+ *                         filters_per_lane is 8); 0 = default (as above;
+ *                         with F given: 8, or 4 with 6 or more filters per
+ *                         lane; fewer when a long delay window would not
+ *                         fit the LDS).
  *   device                HIP device ordinal the bank lives on.
  *   time_chunks           P in {0, 1, 2, 4, ..., 64}; 0 or 1 = off;
  *                         SPIIR_TIME_CHUNKS_AUTO: the library picks P for
