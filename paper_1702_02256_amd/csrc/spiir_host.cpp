@@ -17,10 +17,11 @@ using namespace spiir;
 
 namespace {
 
-// Default launch shape.  The plain sum: 4 filters per lane, 8 waves per
-// group.  The compensated sum spends more per cross-lane addition, so it
-// gains from covering more filters per lane: 6 filters per lane, and with
-// them 4 waves per group (128 VGPRs, 4 groups per CU).
+// Default launch shape of a bank that fills the device (make_plan_fixed
+// takes 4 filters per lane in 4-wave groups for the others).  The plain sum:
+// 4 filters per lane, 8 waves per group.  The compensated sum spends more per
+// cross-lane addition, so it gains from covering more filters per lane: 6
+// filters per lane, and with them 4 waves per group (128 VGPRs).
 constexpr int kDefaultF = 4;
 constexpr int kDefaultFComp = 6;
 constexpr int kDefaultW = 8;
