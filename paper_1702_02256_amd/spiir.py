@@ -105,6 +105,7 @@ def load_library():
         raise ImportError(
             f"{LIB_PATH} is missing: build it with "
             "`python -c 'import __graft_entry__ as g; g.build()'` (there is no fallback path)")
+    _torch_hip_first()
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     sig = {
@@ -322,11 +323,26 @@ def _validate_io(bank, x, z, z_optional=False):
         raise ValueError("z is too small for this block")
 
 
+def _torch_hip_first():
+    """Start torch's HIP runtime before the library makes its first device call.
+
+    The torch wheel ships its own HIP runtime next to the one the library links;
+    when the library's runtime opens the GPU first, torch's finds no device.
+    Started in this order both work on the same device memory."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 class Bank:
     """One template bank bound to one input stream (owns its device memory)."""
 
     def __init__(self, tables, max_block, stream=None, precision="fp32", carry_chunk=0,
                  filters_per_lane=0, waves_per_group=0, device=0, time_chunks=0, window_copies=0):
+        _torch_hip_first()
         lib = load_library()
         self._lib = lib
         hold = _DescHolder(tables, max_block, precision, carry_chunk, filters_per_lane,
