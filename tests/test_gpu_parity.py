@@ -396,7 +396,7 @@ def _random_case(i):
         return tb, max_block, blocks, kw
 
 
-@pytest.mark.parametrize("i", range(16))
+@pytest.mark.parametrize("i", range(48))
 def test_random_configurations_match_the_oracle(i):
     tb, max_block, blocks, kw = _random_case(i)
     x = W.noise_stream(900 + i, sum(blocks))
