@@ -4,9 +4,11 @@
 A step is one block of the whole hot path (input staging and downsample
 cascade, filter bank with carry correction and filter sum, upsample-and-add,
 output write) for every template of the bank, with the state carried from the
-previous block.  The default workload is the multi-rate bank: 4096 templates
-over 7 bands (4096..64 Hz), 40..300 filters per band, 32-tap resampling, 1 s
-blocks.  Prints one JSON line.
+previous block.  The default workload is the serving form: three detector streams
+at 4096 Hz and 16384 multi-rate templates (7 bands, 4096..64 Hz, 40..300
+filters per band, 32-tap resampling) in one bank per stream; the step is one
+1 s block of every stream, and the real-time capacity is measured after it.
+``--config 1..4`` run the other workloads.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -186,27 +188,45 @@ def cpu_baseline(wl, block: int, budget_s: float, gpu_error_blocks: int = 4):
 
 
 def serving_bench(args, S, W, torch, np):
-    """Config 5: three detector streams, one resident multi-rate bank each
-    (16384 templates in total), Poisson block arrivals of 0.125-1 s."""
+    """Config 5, the serving form: three detector streams at 4096 Hz, 16384
+    multi-rate templates (config-3 shape) split into one bank per stream, FP32
+    with the compensated sum.
+
+    1. Saturated step (``value``, roofline): one 1 s block of every stream per
+       batch, back to back, inputs resident in HBM.
+    2. Real-time capacity: k copies of the three banks resident at once
+       (16384 k templates; copies made with spiir_clone, each with its own
+       tables and state), blocks of 0.125-1 s arriving by a Poisson process at
+       real time on every stream, served by the continuous-batching scheduler
+       and, at the same resident count, by the plain form (one block of one
+       bank per launch).  k is bounded by the footprint spiir_footprint gives
+       against the device's free HBM; the largest k whose run keeps up is the
+       capacity, reported with its p50/p99 block latency (arrival to
+       completion on every bank of the stream)."""
     from paper_1702_02256_amd import serving as SV
     n_streams, rate = 3, 4096
     total_t = args.templates or 16384
-    banks = W.serving_banks(n_templates=total_t, n_streams=n_streams)
-    dur = args.serve_seconds
+    tables = W.serving_banks(n_templates=total_t, n_streams=n_streams)
     max_block = 8192
-    # ---- saturated closed loop: one 1 s block of every stream per batch
+    prec = args.precision
+    stream = torch.cuda.Stream()
+    base = [S.Bank(t, max_block, stream=stream, precision=prec, workspace=S.WORKSPACE_CALLER)
+            for t in tables]
+    print(f"serving: {total_t} templates in {n_streams} banks created", file=sys.stderr, flush=True)
+    ws_bytes = max(b.workspace_bytes for b in base)
+
+    # ---- 1. saturated closed loop: one 1 s block of every stream per batch
     K, Wm = args.steps, args.warmup
     blk = rate
     xs_sat = [W.noise_stream(2000 + s, blk * (K + Wm)) for s in range(n_streams)]
     xt = [torch.from_numpy(x.astype(np.float32)).cuda() for x in xs_sat]
-    stream = torch.cuda.Stream()
-    bk = [S.Bank(b, max_block, stream=stream, precision=args.precision) for b in banks]
-    zs = [torch.empty((b.n_templates, blk), dtype=torch.complex64, device="cuda") for b in banks]
-    fs_step = sum(b.filter_samples_per_block(blk) for b in banks)
-    flops = sum(W.algorithmic_flops(b, blk)["filter"] for b in banks)
+    wss = [S.workspace_empty(ws_bytes) for _ in range(n_streams)]
+    zs = [torch.empty((b.n_templates, blk), dtype=torch.complex64, device="cuda") for b in base]
+    fs_step = sum(t.filter_samples_per_block(blk) for t in tables)
+    flops = sum(W.algorithmic_flops(t, blk)["filter"] for t in tables)
     with torch.cuda.stream(stream):
         def step(i):
-            S.spiir_process_batch([(bk[s], xt[s][i * blk:(i + 1) * blk], zs[s])
+            S.spiir_process_batch([(base[s], xt[s][i * blk:(i + 1) * blk], zs[s], wss[s])
                                    for s in range(n_streams)], stream=stream)
         for i in range(Wm):
             step(i)
@@ -222,53 +242,24 @@ def serving_bench(args, S, W, torch, np):
         t1 = time.perf_counter()
     prof = S.spiir_profile_read()
     S.spiir_profile_enable(False)
-    plan = bk[0].plan
-    for b in bk:
-        b.destroy()
+    for b in base:
+        rc, _ = b.status()
+        if rc != 0:
+            raise SystemExit(f"bank status: {S.spiir_strerror(rc)}")
+    plan = base[0].plan
+    del zs, wss
     wall = t1 - t0
+    lat = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(K)])
     filt_ms = prof["filter"]["ms"] / max(prof["filter"]["launches"], 1)
-    if prof["upadd"]["launches"] == 0:
-        flops += sum(W.algorithmic_flops(b, blk)["up"] for b in banks)
-    achieved = flops / (prof["filter"]["launches"] / K) / (filt_ms * 1e-3) / 1e12
+    launches_per_step = prof["filter"]["launches"] / K
+    achieved = flops / launches_per_step / (filt_ms * 1e-3) / 1e12
+    value = fs_step * K / wall
+    workload = f"cfg5-serving-{total_t}x7band-3streams"
+    print(f"serving: saturated step {wall / K * 1e3:.3f} ms, {value:.3e} fs/s", file=sys.stderr, flush=True)
 
-    # ---- open-loop serving: real time, then a replay-speed sweep
-    def serve(policy, speed, seconds):
-        arr = W.serving_arrivals(5005, n_streams, seconds, rate_hz=rate, speed=speed)
-        xs = [W.noise_stream(2100 + s, int(l.sum())) for s, (l, _) in enumerate(arr)]
-        be = SV.HipBackend(xs, n_streams=2, precision=args.precision)
-        sch = SV.Scheduler(be, banks, max_block=max_block, policy=policy)
-        blocks = SV.make_arrivals(arr)
-        st = sch.run(blocks)
-        last = max(b.arrival for b in blocks)
-        for s in range(n_streams):
-            sch.release(s)
-        summ = st.summary()
-        summ["speed"] = speed
-        summ["sustained"] = bool(st.wall <= last + 0.25)
-        print(f"serving {policy} at {speed}x: {summ.get('blocks')} blocks, p99 "
-              f"{summ.get('p99_ms', float('nan')):.1f} ms, sustained {summ['sustained']}",
-              file=sys.stderr, flush=True)
-        return summ
-
-    rt = {pol: serve(pol, 1.0, dur) for pol in ("batched", "plain")}
-    sweep = {"batched": [], "plain": []}
-    cap, cap_slo = {}, {}
-    for pol in ("batched", "plain"):
-        best = 1.0 if rt[pol]["sustained"] else 0.0
-        best_slo = 1.0 if rt[pol]["sustained"] and rt[pol].get("p99_ms", float("inf")) <= args.p99_slo_ms else 0.0
-        for sp in args.serve_speeds:
-            r = serve(pol, sp, max(dur, 2.0 * sp))
-            sweep[pol].append({k: r[k] for k in ("speed", "p50_ms", "p99_ms", "sustained",
-                                                  "requests", "blocks", "batches")})
-            if r["sustained"]:
-                best = max(best, sp)
-                if r.get("p99_ms", float("inf")) <= args.p99_slo_ms:
-                    best_slo = max(best_slo, sp)
-        cap[pol] = best
-        cap_slo[pol] = best_slo
     out = {
         "metric": METRIC,
-        "value": fs_step * K / wall,
+        "value": value,
         "unit": "template-filter-samples/s",
         "n_gpus": 1,
         "steps": K,
@@ -279,33 +270,142 @@ def serving_bench(args, S, W, torch, np):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"cfg5-serving-{total_t}x7band-3streams", "templates": total_t,
-                   "streams": n_streams, "bands": 7, "base_rate_hz": rate,
-                   "saturated_step": "one 1 s block of every stream per batch",
+        "config": {"workload": workload, "templates": total_t, "streams": n_streams, "bands": 7,
+                   "base_rate_hz": rate, "filters": int(sum(t.total_filters for t in tables)),
+                   "saturated_step": "one 1 s block (4096 samples) of every stream per batch",
                    "filters_per_lane": plan["filters_per_lane"],
                    "lanes_per_group": plan["lanes_per_group"], "carry_chunk": plan["carry_chunk"],
-                   "precision": args.precision},
-        "real_time_templates": total_t * cap["batched"],
-        "real_time_templates_plain": total_t * cap["plain"],
-        "real_time_templates_within_p99": {"p99_ms": args.p99_slo_ms,
-                                           "batched": total_t * cap_slo["batched"],
-                                           "plain": total_t * cap_slo["plain"]},
-        "block_latency_ms": {"p50": rt["batched"].get("p50_ms"), "p99": rt["batched"].get("p99_ms"),
-                             "kind": "arrival to completion at real-time arrivals, batched policy",
-                             "plain_p50": rt["plain"].get("p50_ms"), "plain_p99": rt["plain"].get("p99_ms")},
-        "serving_sweep": sweep,
+                   "window_copies": plan["window_copies"], "workspace": "caller", "precision": prec},
+        "block_latency_ms_saturated": {"mean": float(lat.mean()), "p50": float(np.percentile(lat, 50)),
+                                       "p99": float(np.percentile(lat, 99)),
+                                       "kind": "closed loop, back-to-back batches (GPU time per step)"},
+        "fp32_peak_fraction_whole_step": sum(W.algorithmic_flops(t, blk)["total"] for t in tables)
+        / (wall / K) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
         "kernel_ms_per_step": {k: v["ms"] / K for k, v in prof.items()},
         "roofline": {
-            "kernel": "k_filter (filter bank: Eq. 7 recurrence, carry correction, Eq. 8 sum)",
+            "kernel": "k_filter (Eq. 7 recurrence, carry correction, Eq. 8 sum)",
             "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": (lambda t: t and t["bytes_per_launch"])(measured_traffic(workload, "k_filter")),
+            "traffic_detail": measured_traffic(workload, "k_filter"),
+            "algorithmic_flops_per_launch": flops / launches_per_step,
             "avg_launch_ms": filt_ms,
         },
     }
+
+    # ---- 2. real-time capacity
+    if args.serve_seconds > 0:
+        out["serving"] = serving_capacity(args, S, W, SV, torch, np, tables, base, ws_bytes,
+                                          fs_step, value, max_block, prec)
+        cap = out["serving"]
+        out["real_time_templates"] = cap["real_time_templates"]
+        out["real_time_templates_plain"] = cap["real_time_templates_plain"]
+        out["block_latency_ms"] = cap["block_latency_ms"]
+    for b in base:
+        b.destroy()
     if args.cpu_budget > 0:
-        wl = W.Workload("cfg5-bank0", banks[0], rate, K + Wm, 2000)
+        wl = W.Workload(f"{workload}-bank0", tables[0], rate, K + Wm, 2000)
         out["cpu_baseline"] = cpu_baseline(wl, rate, args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+def serving_capacity(args, S, W, SV, torch, np, tables, base, ws_bytes, fs_step, sat_value,
+                     max_block, prec):
+    """Largest resident template count (in copies of the three banks) that the
+    continuous-batching scheduler serves at real-time Poisson arrivals, and the
+    plain form at the same count and at its own largest sustained count."""
+    n_streams = len(tables)
+    per_set = sum(t.n_templates for t in tables)
+    rate = 4096
+    bank_pool = {id(t): [b] for t, b in zip(tables, base)}
+    be_kw = dict(precision=prec, workspace=S.WORKSPACE_CALLER)
+    dur = args.serve_seconds
+    arr = W.serving_arrivals(5005, n_streams, dur, rate_hz=rate, speed=1.0)
+    xs = [W.noise_stream(2100 + s, int(l.sum())) for s, (l, _) in enumerate(arr)]
+
+    def backend():
+        return SV.HipBackend(xs, n_streams=2, pool_templates=max(t.n_templates for t in tables),
+                             pool_workspace=ws_bytes, max_block=max_block, bank_pool=bank_pool,
+                             return_to_pool=True, **be_kw)
+
+    fp_set = sum(S.spiir_footprint(t, max_block, **be_kw) for t in tables)
+    pool_bytes = (2 * 16 * (max(t.n_templates for t in tables) * max_block * 8 + ws_bytes))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    # the three base banks are resident already; each copy needs their
+    # footprint again, each backend its output and workspace pools, and the
+    # allocator rounds every array up: keep 10% back
+    budget = int(0.9 * (free - 1.1 * pool_bytes)) + fp_set
+    k_hbm = max(1, budget // fp_set)
+    # arrival work per copy of the three banks, per second of data
+    fs_per_set_s = fs_step  # one 1 s block of every stream = one second of data
+    k_est = sat_value / fs_per_set_s
+    print(f"capacity: footprint {fp_set / per_set / 1024:.1f} KiB/template, HBM admits {k_hbm} copies "
+          f"({k_hbm * per_set} templates), saturated rate sustains ~{k_est:.0f}", file=sys.stderr, flush=True)
+
+    def trial(policy, k):
+        units = [(s, tables[s]) for _ in range(k) for s in range(n_streams)]
+        be = backend()
+        sch = SV.Scheduler(be, units=units, max_block=max_block, hbm_budget=budget, policy=policy,
+                           abort_backlog_s=args.serve_backlog_s)
+        st = sch.run(SV.make_arrivals(arr))
+        sch.release_all()
+        torch.cuda.synchronize()
+        summ = st.summary()
+        summ.update(copies=k, templates=k * per_set, policy=policy,
+                    sustained=bool(not st.aborted and summ["drain_s"] <= args.serve_drain_s))
+        print(f"capacity {policy} k={k} ({k * per_set} templates): sustained {summ['sustained']}, "
+              f"blocks {summ['blocks']}/{summ['blocks_arrived']}, p50 {summ.get('p50_ms', float('nan')):.0f} ms, "
+              f"p99 {summ.get('p99_ms', float('nan')):.0f} ms, drain {summ['drain_s']:.2f} s",
+              file=sys.stderr, flush=True)
+        del be
+        return summ
+
+    def next_k(r, k):
+        """After a run that fell behind: the count its served rate would carry
+        (98%), and at least 3% fewer copies."""
+        served = r["filter_samples_per_s"] / fs_per_set_s
+        return max(1, min(k - 1, int(k * 0.97), int(0.98 * served)))
+
+    def search(policy, k_hi, first=None):
+        """Descend from k_hi until a run keeps up (`first`: a run at k_hi already made)."""
+        runs, k = [], max(1, min(k_hi, k_hbm))
+        while True:
+            r = first if first is not None and first["copies"] == k else trial(policy, k)
+            first = None
+            runs.append(r)
+            if r["sustained"] or k == 1:
+                return (k if r["sustained"] else 0), runs
+            k = next_k(r, k)
+
+    k_b, runs_b = search("batched", int(np.ceil(k_est * 1.02)))
+    plain_same = trial("plain", k_b) if k_b > 0 else None
+    k_p, runs_p = (search("plain", k_b, first=plain_same) if plain_same and plain_same["sustained"]
+                   else search("plain", next_k(plain_same, k_b)) if k_b > 0 else (0, []))
+    best_b = next((r for r in runs_b if r["copies"] == k_b), None)
+    best_p = next((r for r in runs_p if r["copies"] == k_p), None)
+    keys = ("copies", "templates", "sustained", "aborted", "p50_ms", "p99_ms", "max_ms", "drain_s",
+            "blocks", "blocks_arrived", "requests", "batches", "filter_samples_per_s")
+    pick = lambda r: {k: r.get(k) for k in keys} if r else None
+    return {
+        "real_time_templates": k_b * per_set,
+        "real_time_templates_plain": k_p * per_set,
+        "binding_limit": ("HBM footprint" if k_b >= k_hbm else "device throughput"),
+        "hbm_admits_templates": int(k_hbm * per_set),
+        "footprint_bytes_per_template": fp_set / per_set,
+        "block_latency_ms": {
+            "p50": best_b and best_b.get("p50_ms"), "p99": best_b and best_b.get("p99_ms"),
+            "kind": "arrival to completion on every bank of the stream, real-time Poisson arrivals, "
+                    "batched policy at its capacity",
+            "plain_same_count": pick(plain_same),
+            "plain_at_own_capacity": pick(best_p)},
+        "runs": {"batched": [pick(r) for r in runs_b], "plain": [pick(r) for r in runs_p]},
+        "definition": (f"{dur:g} s of data per stream at real time; a run keeps up if its backlog "
+                       f"(oldest unfinished block) stays under {args.serve_backlog_s:g} s and it ends "
+                       f"within {args.serve_drain_s:g} s of the last arrival"),
+        "output": "z written to pooled buffers (one per device stream and batch slot)",
+    }
 
 
 def main():
@@ -314,13 +414,15 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=50,
                     help="untimed blocks first; the clocks settle after about 30")
-    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5])
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
-                    help="seconds of data per stream in the real-time serving run (config 5)")
-    ap.add_argument("--p99-slo-ms", type=float, default=50.0,
-                    help="serving: p99 block latency bound for the within-p99 capacity")
-    ap.add_argument("--serve-speeds", type=float, nargs="*", default=[60, 120, 140, 160, 170, 180, 200],
-                    help="replay speeds of the capacity sweep (config 5)")
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="config 5: seconds of data per stream in each real-time capacity run "
+                         "(0 = saturated step only)")
+    ap.add_argument("--serve-backlog-s", type=float, default=3.0,
+                    help="config 5: a capacity run stops once its oldest unfinished block is this old")
+    ap.add_argument("--serve-drain-s", type=float, default=1.5,
+                    help="config 5: a capacity run keeps up if it ends within this long after "
+                         "the last arrival")
     ap.add_argument("--templates", type=int, default=None)
     ap.add_argument("--filters-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)

@@ -126,6 +126,18 @@ enum {
  *                         one (two 32-bit accesses, half the LDS, so long
  *                         delay windows leave room for more workgroups per
  *                         compute unit).  Results do not depend on it.
+ *   workspace             SPIIR_WORKSPACE_OWN (0): spiir_create allocates the
+ *                         bank's workspace (the per-piece band outputs that
+ *                         the filter kernel hands to the upsample-and-add
+ *                         kernel within one launch sequence).
+ *                         SPIIR_WORKSPACE_CALLER (1): it does not; every
+ *                         request on the bank must then bring a workspace
+ *                         (spiir_request.ws_dev), and the footprint leaves
+ *                         it out.  The workspace holds nothing between launch
+ *                         sequences, so a caller can keep a few of them for
+ *                         many banks (one per launch sequence in flight)
+ *                         instead of one per bank.  Results do not depend on
+ *                         where the workspace lives.
  */
 typedef struct {
     int32_t n_templates;
@@ -147,6 +159,7 @@ typedef struct {
     int32_t device;
     int32_t time_chunks;
     int32_t window_copies;
+    int32_t workspace;
 } spiir_bank_desc;
 
 #define SPIIR_MAX_BANDS 12
@@ -154,14 +167,25 @@ typedef struct {
 #define SPIIR_MAX_TAPS 1024
 #define SPIIR_MAX_BATCH 16
 #define SPIIR_TIME_CHUNKS_AUTO (-1)
+#define SPIIR_WORKSPACE_OWN 0
+#define SPIIR_WORKSPACE_CALLER 1
 
-/* One request of a batch: the next n samples of the stream bound to `bank`. */
+/*
+ * One request of a batch: the next n samples of the stream bound to `bank`.
+ *   ws_dev  device workspace for this request, or NULL for the bank's own
+ *           (SPIIR_EINVAL if the bank has none).  At least the bank's
+ *           spiir_plan_info.workspace_bytes, 256-byte aligned, caller-owned;
+ *           no other request or launch sequence may use it until this one's
+ *           work has completed (reuse in stream order is fine).  Its contents
+ *           before and after the call do not matter.
+ */
 typedef struct {
     spiir_bank* bank;
     const float* x_dev;
     int64_t n;
     spiir_c32* z_dev;
     int64_t ldz;
+    void* ws_dev;
 } spiir_request;
 
 /*
@@ -184,6 +208,17 @@ int spiir_footprint(const spiir_bank_desc* desc, size_t* bytes);
 int spiir_create(const spiir_bank_desc* desc, void* hip_stream, spiir_bank** out);
 
 /*
+ * spiir_clone — a new bank with the tables, launch plan and workspace mode of
+ * `src` (its own device copy of every table) and zero state, bound to a
+ * stream of its own; as if spiir_create had been called again with src's
+ * descriptor, without planning again or reading host tables.  For serving
+ * one template bank on several detector streams (the paper's search runs
+ * the same bank per detector, §5).  Waits for src's outstanding work; src is
+ * not changed.  Same error codes as spiir_create (*out NULL on error).
+ */
+int spiir_clone(const spiir_bank* src, void* hip_stream, spiir_bank** out);
+
+/*
  * spiir_process_block — filter the next n samples of the bank's stream
  * (Eqs. 7-8, and the §2.2 chain when H > 1).
  *   x_dev  device pointer, n FP32 samples at the base rate (caller-owned).
@@ -198,6 +233,7 @@ int spiir_create(const spiir_bank_desc* desc, void* hip_stream, spiir_bank** out
  */
 int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
                         int64_t ldz, void* hip_stream);
+
 
 /*
  * spiir_process_batch — one launch sequence over up to SPIIR_MAX_BATCH
@@ -326,6 +362,8 @@ typedef struct {
     size_t footprint;         /* device bytes spiir_create allocates           */
     int32_t time_chunks;      /* P (1 = no time split)                         */
     int32_t window_copies;    /* LDS copies of the input window (1 or 2)       */
+    size_t workspace_bytes;   /* device workspace one request needs            */
+    int32_t workspace;        /* SPIIR_WORKSPACE_OWN or SPIIR_WORKSPACE_CALLER */
 } spiir_plan_info;
 
 int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info);

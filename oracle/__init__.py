@@ -70,11 +70,6 @@ def _cplx_pairs(a) -> np.ndarray:
     return a.view(np.float64)
 
 
-def set_threads(n: int) -> None:
-    """OpenMP threads for the oracle (affects calls made after the first load)."""
-    os.environ["OMP_NUM_THREADS"] = str(int(n))
-
-
 class OracleBank:
     """Streaming FP64 bank: ``process(x)`` consumes the next block of the stream."""
 

@@ -60,6 +60,8 @@ struct Plan {
     int nrun_max = 1, npiece_max = 1;
     int lds_filter = 0, lds_stage = 0, lds_up = 0;
     int64_t total_filters = 0, n_slots = 0, zw_elems = 0, ring_total = 0;
+    int workspace = SPIIR_WORKSPACE_OWN;
+    int32_t n_groups = 0, n_pieces = 0;  // kept after the layout arrays are released
     std::vector<int> maxd_band, S, ring_mask;
     std::vector<int64_t> ring_off;
     std::vector<int64_t> zstride;   // workspace row per piece, per band (even length)
@@ -71,6 +73,7 @@ struct Plan {
     std::vector<int64_t> slot_src;  // desc filter index, -1 = padding
     std::vector<int32_t> slot_off;
     size_t footprint = 0;
+    uint64_t layout = 0;  // layout_fingerprint, taken before the arrays are released
 };
 
 bool finite_all(const double* p, int64_t n)
@@ -100,6 +103,7 @@ int validate(const spiir_bank_desc* d)
         (d->time_chunks < 0 || d->time_chunks > 64 || (d->time_chunks & (d->time_chunks - 1)) != 0))
         return SPIIR_EINVAL;
     if (d->window_copies < 0 || d->window_copies > 2) return SPIIR_EINVAL;
+    if (d->workspace != SPIIR_WORKSPACE_OWN && d->workspace != SPIIR_WORKSPACE_CALLER) return SPIIR_EINVAL;
     int64_t total = 0;
     for (int64_t s = 0; s < (int64_t)d->n_templates * H; ++s) {
         if (d->n_filters[s] < 0) return SPIIR_EINVAL;
@@ -134,6 +138,7 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub, int copie
     p.L = 64 * p.W;
     p.C = d->carry_chunk ? d->carry_chunk : kDefaultC;
     p.precision = d->precision;
+    p.workspace = d->workspace;
     p.max_block = d->max_block;
     p.mb_inner = std::min(d->max_block, kInnerBlock);
     p.td = p.H > 1 ? d->n_taps_down : 1;
@@ -382,12 +387,14 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub, int copie
     fp += p.wg.size() * sizeof(WgDesc) + p.piece.size() * sizeof(PieceDesc);
     fp += p.seg.size() * sizeof(SegDesc) + p.lane_meta.size() * sizeof(int32_t);
     fp += (size_t)p.ring_total * sizeof(float) + (size_t)(p.td + p.tu) * sizeof(float);
-    fp += (size_t)p.zw_elems * sizeof(c32);
+    if (p.workspace == SPIIR_WORKSPACE_OWN) fp += (size_t)p.zw_elems * sizeof(c32);
     fp += (size_t)T * H * p.hu_len * sizeof(c32) + (size_t)T * sizeof(int32_t) + sizeof(BankDev);
     fp += 2 * sizeof(int64_t);
     if (p.P > 1)  // a1^lc, end states, chained states, entering chunk-start state, exponents
         fp += (size_t)p.n_slots * sizeof(c32) * (1 + 2 * (size_t)(p.P + 1) + 1);
     p.footprint = fp;
+    p.n_groups = (int32_t)p.wg.size();
+    p.n_pieces = (int32_t)p.piece.size();
     return SPIIR_OK;
 }
 
@@ -659,6 +666,12 @@ int zero_state(spiir_bank* b, hipStream_t s)
     return e;
 }
 
+// Bytes of one request's workspace (the per-piece band outputs of one chunk).
+size_t workspace_bytes(const Plan& p)
+{
+    return ((size_t)p.zw_elems * sizeof(c32) + 255) & ~(size_t)255;
+}
+
 int64_t state_bytes(const Plan& p)
 {
     return kStateHeaderBytes + p.n_slots * 2 * (int64_t)sizeof(c32) + p.ring_total * (int64_t)sizeof(float) +
@@ -711,6 +724,7 @@ int validate_batch(int32_t n_req, const spiir_request* req, spiir_peak* const* p
         if (peaks && !peaks[r]) return SPIIR_EINVAL;
         if (q.z_dev ? q.ldz < q.n : !peaks) return SPIIR_EINVAL;
         if (q.bank->device != req[0].bank->device) return SPIIR_EINVAL;
+        if (q.ws_dev ? ((uintptr_t)q.ws_dev & 255u) != 0 : !q.bank->zw) return SPIIR_EINVAL;
         for (int s = 0; s < r; ++s)
             if (req[s].bank == q.bank) return SPIIR_EORDER;
     }
@@ -751,6 +765,7 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
             ReqArg& ra = A.req[k];
             ra.bd = b->bd;
             ra.x = q.x_dev + c0;
+            ra.zw = q.ws_dev ? static_cast<c32*>(q.ws_dev) : b->zw;
             ra.z = q.z_dev ? reinterpret_cast<c32*>(q.z_dev) + c0 : nullptr;
             ra.ldz = q.ldz;
             ra.peaks = peaks ? peaks[r] : nullptr;
@@ -768,7 +783,8 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
         struct Shape {
             int F, L, prec;
         };
-        std::vector<Shape> shapes;
+        Shape shape_buf[kMaxReq];
+        int nshape = 0;
         auto shape_of = [&](int k) {
             const Plan& p = req[rmap[k]].bank->plan;
             return Shape{p.F, p.L, p.precision};
@@ -776,9 +792,10 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
         auto same = [](const Shape& a, const Shape& b) { return a.F == b.F && a.L == b.L && a.prec == b.prec; };
         for (int k = 0; k < A.nreq; ++k) {
             bool seen = false;
-            for (const Shape& sh : shapes) seen |= same(sh, shape_of(k));
-            if (!seen) shapes.push_back(shape_of(k));
+            for (int i = 0; i < nshape; ++i) seen |= same(shape_buf[i], shape_of(k));
+            if (!seen) shape_buf[nshape++] = shape_of(k);
         }
+        const Shape* const shapes_end = shape_buf + nshape;
         // filter workgroups of one shape: band-major across requests (longest
         // bands first), chunk-major inside a (band, request) segment when split
         // in time
@@ -843,14 +860,16 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
         e = (hipError_t)launch_stage(A, lds_s, s);
         mark(1);
         if (split)
-            for (const Shape& sh : shapes) {
+            for (const Shape* sp = shape_buf; sp != shapes_end; ++sp) {
+                const Shape& sh = *sp;
                 LaunchArgs X = A;
                 const int n1 = segments(X, true, sh);
                 if (e == hipSuccess && n1 > 0)
                     e = (hipError_t)launch_filter_local(sh.F, sh.prec, X, n1, sh.L, shape_lds(sh, true), s);
             }
         if (e == hipSuccess && split && nchain > 0) e = (hipError_t)launch_chain(A2, nchain, s);
-        for (const Shape& sh : shapes) {
+        for (const Shape* sp = shape_buf; sp != shapes_end; ++sp) {
+            const Shape& sh = *sp;
             LaunchArgs X = A;
             const int n0 = segments(X, false, sh);
             if (e == hipSuccess && n0 > 0)
@@ -916,8 +935,8 @@ static void fill_plan_info(const Plan& p, spiir_plan_info* info)
 {
     info->total_filters = p.total_filters;
     info->filter_slots = p.n_slots;
-    info->n_groups = (int32_t)p.wg.size();
-    info->n_pieces = (int32_t)p.piece.size();
+    info->n_groups = p.n_groups;
+    info->n_pieces = p.n_pieces;
     info->lanes_per_group = p.L;
     info->filters_per_lane = p.F;
     info->lds_bytes = p.lds_filter;
@@ -925,6 +944,8 @@ static void fill_plan_info(const Plan& p, spiir_plan_info* info)
     info->footprint = p.footprint;
     info->time_chunks = p.P;
     info->window_copies = p.copies;
+    info->workspace_bytes = workspace_bytes(p);
+    info->workspace = p.workspace;
 }
 
 int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info)
@@ -959,36 +980,11 @@ int spiir_footprint(const spiir_bank_desc* desc, size_t* bytes)
     return SPIIR_OK;
 }
 
-int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
+// Device arrays of a bank, sized from its plan (which may already have
+// released its layout arrays: only counts are read here).
+static bool alloc_bank(spiir_bank* b)
 {
-    if (!out) return SPIIR_EINVAL;
-    *out = nullptr;
-    spiir_bank* b = nullptr;
-    try {
-        b = new spiir_bank();
-        int rc = make_plan(desc, b->plan);
-        if (rc) {
-            delete b;
-            return rc;
-        }
-    } catch (const std::bad_alloc&) {
-        delete b;
-        return SPIIR_ENOMEM;
-    }
-    Plan& p = b->plan;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device >= ndev) {
-        delete b;
-        return ndev == 0 ? SPIIR_EDEVICE : SPIIR_EINVAL;
-    }
-    b->device = desc->device;
-    if (hipSetDevice(b->device) != hipSuccess || allow_filter_lds() != 0) {
-        (void)hipGetLastError();
-        delete b;
-        return SPIIR_EDEVICE;
-    }
-    hipStream_t s = (hipStream_t)stream;
-
+    const Plan& p = b->plan;
     bool ok = true;
     ok &= dalloc(&b->a, p.n_slots) == hipSuccess;
     ok &= dalloc(&b->b, p.n_slots) == hipSuccess;
@@ -996,14 +992,14 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     ok &= dalloc(&b->y, p.n_slots) == hipSuccess;
     ok &= dalloc(&b->ys, p.n_slots) == hipSuccess;
     ok &= dalloc(&b->off, p.n_slots) == hipSuccess;
-    ok &= dalloc(&b->wg, p.wg.size()) == hipSuccess;
-    ok &= dalloc(&b->piece, p.piece.size()) == hipSuccess;
-    ok &= dalloc(&b->seg, p.seg.size()) == hipSuccess;
-    ok &= dalloc(&b->lane_meta, p.lane_meta.size()) == hipSuccess;
+    ok &= dalloc(&b->wg, p.n_groups) == hipSuccess;
+    ok &= dalloc(&b->piece, p.n_pieces) == hipSuccess;
+    ok &= dalloc(&b->seg, (size_t)p.T * p.H) == hipSuccess;
+    ok &= dalloc(&b->lane_meta, (size_t)p.n_groups * p.L) == hipSuccess;
     ok &= dalloc(&b->rings, p.ring_total) == hipSuccess;
     ok &= dalloc(&b->hd, p.td) == hipSuccess;
     ok &= dalloc(&b->hu, p.tu) == hipSuccess;
-    ok &= dalloc(&b->zw, p.zw_elems) == hipSuccess;
+    if (p.workspace == SPIIR_WORKSPACE_OWN) ok &= dalloc(&b->zw, p.zw_elems) == hipSuccess;
     ok &= dalloc(&b->uphist, (size_t)p.T * p.H * p.hu_len) == hipSuccess;
     ok &= dalloc(&b->flags, p.T) == hipSuccess;
     ok &= dalloc(&b->clock, 2) == hipSuccess;
@@ -1015,31 +1011,14 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     }
     ok &= dalloc(&b->bd, 1) == hipSuccess;
     ok &= hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) == hipSuccess;
-    if (!ok) {
-        (void)hipGetLastError();
-        free_bank(b);
-        return SPIIR_ENOMEM;
-    }
+    if (!ok) (void)hipGetLastError();
+    return ok;
+}
 
-    // tables in lane order; coefficients go through the FP64 prep kernel
-    c64* da = nullptr;
-    c64* db = nullptr;
-    std::vector<c64> ha((size_t)p.n_slots), hb((size_t)p.n_slots);
-    for (int64_t g = 0; g < p.n_slots; ++g) {
-        const int64_t src = p.slot_src[g];
-        if (src >= 0) {
-            ha[g] = c64{desc->a1[2 * src], desc->a1[2 * src + 1]};
-            hb[g] = c64{desc->b0[2 * src], desc->b0[2 * src + 1]};
-        } else {
-            ha[g] = c64{0.0, 0.0};
-            hb[g] = c64{0.0, 0.0};
-        }
-    }
-    std::vector<float> hd(p.td, 1.0f), hu(p.tu, 1.0f);
-    if (p.H > 1) {
-        for (int i = 0; i < p.td; ++i) hd[i] = (float)desc->h_down[i];
-        for (int i = 0; i < p.tu; ++i) hu[i] = (float)desc->h_up[i];
-    }
+// The device-side description of a bank: its plan's sizes and its arrays.
+static BankDev bank_dev(const spiir_bank* b)
+{
+    const Plan& p = b->plan;
     BankDev bd{};
     bd.T = p.T;
     bd.H = p.H;
@@ -1086,6 +1065,84 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     bd.uend = b->uend;
     bd.schain = b->schain;
     bd.ys0 = b->ys0;
+    return bd;
+}
+
+// After upload the per-slot layout arrays live on the device only: the host
+// keeps their fingerprint (state blobs) and counts, not the arrays.
+static void release_layout(Plan& p)
+{
+    p.layout = layout_fingerprint(p);
+    std::vector<WgDesc>().swap(p.wg);
+    std::vector<PieceDesc>().swap(p.piece);
+    std::vector<SegDesc>().swap(p.seg);
+    std::vector<int32_t>().swap(p.lane_meta);
+    std::vector<int64_t>().swap(p.slot_src);
+    std::vector<int32_t>().swap(p.slot_off);
+}
+
+int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
+{
+    if (!out) return SPIIR_EINVAL;
+    *out = nullptr;
+    spiir_bank* b = nullptr;
+    try {
+        b = new spiir_bank();
+        int rc = make_plan(desc, b->plan);
+        if (rc) {
+            delete b;
+            return rc;
+        }
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return SPIIR_ENOMEM;
+    }
+    Plan& p = b->plan;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device >= ndev) {
+        (void)hipGetLastError();
+        delete b;
+        return ndev == 0 ? SPIIR_EDEVICE : SPIIR_EINVAL;
+    }
+    b->device = desc->device;
+    if (hipSetDevice(b->device) != hipSuccess || allow_filter_lds() != 0) {
+        (void)hipGetLastError();
+        delete b;
+        return SPIIR_EDEVICE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!alloc_bank(b)) {
+        free_bank(b);
+        return SPIIR_ENOMEM;
+    }
+
+    // tables in lane order; coefficients go through the FP64 prep kernel
+    c64* da = nullptr;
+    c64* db = nullptr;
+    std::vector<c64> ha, hb;
+    try {
+        ha.resize((size_t)p.n_slots);
+        hb.resize((size_t)p.n_slots);
+    } catch (const std::bad_alloc&) {
+        free_bank(b);
+        return SPIIR_ENOMEM;
+    }
+    for (int64_t g = 0; g < p.n_slots; ++g) {
+        const int64_t src = p.slot_src[g];
+        if (src >= 0) {
+            ha[g] = c64{desc->a1[2 * src], desc->a1[2 * src + 1]};
+            hb[g] = c64{desc->b0[2 * src], desc->b0[2 * src + 1]};
+        } else {
+            ha[g] = c64{0.0, 0.0};
+            hb[g] = c64{0.0, 0.0};
+        }
+    }
+    std::vector<float> hd(p.td, 1.0f), hu(p.tu, 1.0f);
+    if (p.H > 1) {
+        for (int i = 0; i < p.td; ++i) hd[i] = (float)desc->h_down[i];
+        for (int i = 0; i < p.tu; ++i) hu[i] = (float)desc->h_up[i];
+    }
+    const BankDev bd = bank_dev(b);
 
     hipError_t e = hipSuccess;
     auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -1138,6 +1195,61 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
         free_bank(b);
         return SPIIR_EDEVICE;
     }
+    release_layout(p);
+    *out = b;
+    return SPIIR_OK;
+}
+
+int spiir_clone(const spiir_bank* src, void* stream, spiir_bank** out)
+{
+    if (!out) return SPIIR_EINVAL;
+    *out = nullptr;
+    if (!src) return SPIIR_EINVAL;
+    if (src->poisoned) return SPIIR_EDEVICE;
+    spiir_bank* b = nullptr;
+    try {
+        b = new spiir_bank();
+        b->plan = src->plan;  // sizes and counts only: the layout arrays were released
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return SPIIR_ENOMEM;
+    }
+    b->device = src->device;
+    if (hipSetDevice(b->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return SPIIR_EDEVICE;
+    }
+    if (!alloc_bank(b)) {
+        free_bank(b);
+        return SPIIR_ENOMEM;
+    }
+    const Plan& p = b->plan;
+    hipStream_t s = (hipStream_t)stream;
+    const BankDev bd = bank_dev(b);
+    hipError_t e = src->ev_recorded ? hipStreamWaitEvent(s, src->ev, 0) : hipSuccess;
+    auto dd = [&](void* dst, const void* from, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, from, bytes, hipMemcpyDeviceToDevice, s);
+    };
+    dd(b->a, src->a, sizeof(c32) * p.n_slots);
+    dd(b->b, src->b, sizeof(c32) * p.n_slots);
+    dd(b->dc, src->dc, sizeof(c32) * p.n_slots);
+    dd(b->off, src->off, sizeof(int32_t) * p.n_slots);
+    dd(b->wg, src->wg, sizeof(WgDesc) * p.n_groups);
+    dd(b->piece, src->piece, sizeof(PieceDesc) * p.n_pieces);
+    dd(b->seg, src->seg, sizeof(SegDesc) * (size_t)p.T * p.H);
+    dd(b->lane_meta, src->lane_meta, sizeof(int32_t) * (size_t)p.n_groups * p.L);
+    dd(b->hd, src->hd, sizeof(float) * p.td);
+    dd(b->hu, src->hu, sizeof(float) * p.tu);
+    if (p.P > 1) dd(b->al, src->al, sizeof(c32) * p.n_slots);
+    if (e == hipSuccess && (e = hipMemcpyAsync(b->bd, &bd, sizeof(BankDev), hipMemcpyHostToDevice, s)) == hipSuccess)
+        e = (hipError_t)zero_state(b, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_bank(b);
+        return SPIIR_EDEVICE;
+    }
     *out = b;
     return SPIIR_OK;
 }
@@ -1161,7 +1273,7 @@ int spiir_process_batch(int32_t n_req, const spiir_request* req, void* stream)
 int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
                         int64_t ldz, void* stream)
 {
-    spiir_request r{bank, x_dev, n, z_dev, ldz};
+    spiir_request r{bank, x_dev, n, z_dev, ldz, nullptr};
     return spiir_process_batch(1, &r, stream);
 }
 
@@ -1187,7 +1299,7 @@ int spiir_process_batch_peaks(int32_t n_req, const spiir_request* req, spiir_pea
 int spiir_process_peaks(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
                         int64_t ldz, spiir_peak* peak_dev, float threshold, void* stream)
 {
-    spiir_request r{bank, x_dev, n, z_dev, ldz};
+    spiir_request r{bank, x_dev, n, z_dev, ldz, nullptr};
     spiir_peak* pk[1] = {peak_dev};
     return spiir_process_batch_peaks(1, &r, pk, threshold, stream);
 }
@@ -1236,7 +1348,7 @@ int spiir_save_state(spiir_bank* b, void* host_buf, void* stream)
     if (b->ev_recorded) e = hipStreamWaitEvent(s, b->ev, 0);
     StateHeader hdr{kStateMagic, kStateVersion, p.T, p.H, p.F, p.L, p.C, p.precision,
                     p.n_slots, p.ring_total, b->done, (int64_t)p.T * p.H * p.hu_len,
-                    layout_fingerprint(p)};
+                    p.layout};
     char* o = (char*)host_buf;
     std::memset(o, 0, kStateHeaderBytes);
     std::memcpy(o, &hdr, sizeof(hdr));
@@ -1268,7 +1380,7 @@ int spiir_load_state(spiir_bank* b, const void* host_buf, void* stream)
     if (hdr.magic != kStateMagic || hdr.version != kStateVersion || hdr.T != p.T || hdr.H != p.H ||
         hdr.F != p.F || hdr.L != p.L || hdr.C != p.C || hdr.n_slots != p.n_slots ||
         hdr.ring_total != p.ring_total || hdr.hist != (int64_t)p.T * p.H * p.hu_len || hdr.done < 0 ||
-        hdr.done % (1 << (p.H - 1)) != 0 || hdr.layout != layout_fingerprint(p))
+        hdr.done % (1 << (p.H - 1)) != 0 || hdr.layout != p.layout)
         return SPIIR_EINVAL;
     int rc = bank_sync(b);
     if (rc) return rc;

@@ -98,7 +98,7 @@ struct BankDev {
     float* rings;                   // per-band input history rings
     const float* hd;
     const float* hu;
-    c32* zw;                        // per-piece band outputs of the current block
+    c32* zw;                        // the bank's own workspace (null with a caller workspace)
     c32* uphist;                    // [T][H][hu_len] last acc samples per band
     int32_t* flags;                 // [T] sticky non-finite flags
     // [0]: absolute base-rate index of the first sample of the chunk being
@@ -119,6 +119,7 @@ struct BankDev {
 struct ReqArg {
     const BankDev* bd;
     const float* x;
+    c32* zw;             // workspace: per-piece band outputs of the current chunk
     c32* z;              // null: the output is not written
     int64_t ldz;
     spiir_peak* peaks;   // null: no trigger reduction
@@ -139,6 +140,9 @@ struct LaunchArgs {
     int16_t seg_band[kMaxReq * kMaxBands];
     int32_t tcum[kMaxReq + 1];                     // prefix of templates
 };
+
+// Kernel arguments are limited to 4 KiB.
+static_assert(sizeof(LaunchArgs) <= 4096, "launch arguments exceed the kernel argument limit");
 
 // Launchers (spiir_kernels.hip).  All return hipError_t as int.
 int launch_stage(const LaunchArgs& a, int lds_bytes, void* stream);

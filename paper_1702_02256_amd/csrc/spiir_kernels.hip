@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
     const int S = bd->S[h];
     const SPIIR_AS_CONST float* ring = cmem(bd->rings) + bd->ring_off[h];
     const int64_t mk = bd->ring_mask[h];
-    SPIIR_AS_GLOBAL c32* zwg = gmem(bd->zw);
+    SPIIR_AS_GLOBAL c32* zwg = gmem(q.zw);
     // Lanes come in pairs of one run (segments span an even number of lanes).
     // The pair sum of sample j is entry e = lane/2 of row j: pbuf[e*(kTile+1) + j],
     // the even lane storing its real part and the odd lane its imaginary part.
@@ -726,7 +726,7 @@ __global__ void __launch_bounds__(kUpThreads, 4) k_upadd(LaunchArgs args)
     const int tid = threadIdx.x;
     const int H = bd->H, n = q.n, HU = bd->hu_len, tu = bd->tu, MB = bd->max_block;
     const SPIIR_AS_CONST SegDesc* seg = cmem(bd->seg) + (int64_t)t * H;
-    const SPIIR_AS_CONST c32* zw = cmem(bd->zw);
+    const SPIIR_AS_CONST c32* zw = cmem(q.zw);
     SPIIR_AS_GLOBAL c32* zrow = q.z ? gmem(q.z) + (int64_t)t * q.ldz : nullptr;
     const bool peaks = q.peaks != nullptr;
     PeakAcc acc;

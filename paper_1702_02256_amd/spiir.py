@@ -28,6 +28,8 @@ SPIIR_FP32 = 0
 SPIIR_FP32_COMPENSATED = 1
 MAX_BATCH = 16
 TIME_CHUNKS_AUTO = -1  # time_chunks: the library chooses the split
+WORKSPACE_OWN = 0      # spiir_create allocates the bank's workspace
+WORKSPACE_CALLER = 1   # every request brings one (spiir_request.ws_dev)
 
 _PRECISION = {"fp32": SPIIR_FP32, "fp32_compensated": SPIIR_FP32_COMPENSATED,
               "compensated": SPIIR_FP32_COMPENSATED}
@@ -54,6 +56,7 @@ class BankDesc(C.Structure):
         ("device", C.c_int32),
         ("time_chunks", C.c_int32),
         ("window_copies", C.c_int32),
+        ("workspace", C.c_int32),
     ]
 
 
@@ -64,6 +67,7 @@ class Request(C.Structure):
         ("n", C.c_int64),
         ("z_dev", C.c_void_p),
         ("ldz", C.c_int64),
+        ("ws_dev", C.c_void_p),
     ]
 
 
@@ -80,6 +84,8 @@ class PlanInfo(C.Structure):
         ("footprint", C.c_size_t),
         ("time_chunks", C.c_int32),
         ("window_copies", C.c_int32),
+        ("workspace_bytes", C.c_size_t),
+        ("workspace", C.c_int32),
     ]
 
 
@@ -111,6 +117,7 @@ def load_library():
     sig = {
         "spiir_footprint": (C.c_int, [C.POINTER(BankDesc), C.POINTER(C.c_size_t)]),
         "spiir_create": (C.c_int, [C.POINTER(BankDesc), vp, C.POINTER(vp)]),
+        "spiir_clone": (C.c_int, [vp, vp, C.POINTER(vp)]),
         "spiir_process_block": (C.c_int, [vp, vp, i64, vp, i64, vp]),
         "spiir_process_batch": (C.c_int, [i32, C.POINTER(Request), vp]),
         "spiir_reset": (C.c_int, [vp]),
@@ -168,7 +175,7 @@ class _DescHolder:
     """A BankDesc plus the numpy arrays its pointers refer to."""
 
     def __init__(self, tables, max_block, precision="fp32", carry_chunk=0, filters_per_lane=0,
-                 waves_per_group=0, device=0, time_chunks=0, window_copies=0):
+                 waves_per_group=0, device=0, time_chunks=0, window_copies=0, workspace=WORKSPACE_OWN):
         self.nf = np.ascontiguousarray(tables.n_filters.reshape(-1), dtype=np.int32)
         self.a1 = np.ascontiguousarray(np.asarray(tables.a1, np.complex128)).view(np.float64)
         self.b0 = np.ascontiguousarray(np.asarray(tables.b0, np.complex128)).view(np.float64)
@@ -187,7 +194,8 @@ class _DescHolder:
             n_taps_up=len(self.hu), h_up=dp(self.hu),
             max_block=int(max_block), precision=prec, carry_chunk=int(carry_chunk),
             filters_per_lane=int(filters_per_lane), waves_per_group=int(waves_per_group),
-            device=int(device), time_chunks=int(time_chunks), window_copies=int(window_copies))
+            device=int(device), time_chunks=int(time_chunks), window_copies=int(window_copies),
+            workspace=int(workspace))
 
 
 # ---------------------------------------------------------------- C-named functions
@@ -215,13 +223,38 @@ def spiir_process_block(bank: "Bank", x, z, stream=None) -> None:
     bank.process_block(x, z, stream)
 
 
+def _ws_ptr(bank, ws):
+    """Device address of a caller workspace (a torch tensor or an int), or None."""
+    if ws is None:
+        return None
+    if isinstance(ws, int):
+        return ws
+    if not ws.is_cuda or ws.numel() * ws.element_size() < bank.workspace_bytes:
+        raise ValueError("the workspace must be a device tensor of at least workspace_bytes")
+    return ws.data_ptr()
+
+
+def _request(item, z_optional=False):
+    """(bank, x, z[, ws]) -> Request; z may be None where z_optional."""
+    bank, x, z = item[:3]
+    ws = item[3] if len(item) > 3 else None
+    _validate_io(bank, x, z, z_optional=z_optional)
+    return Request(bank._h, x.data_ptr(), int(x.numel()), z.data_ptr() if z is not None else None,
+                   int(z.stride(0)) if z is not None else 0, _ws_ptr(bank, ws))
+
+
+def workspace_empty(nbytes: int, device="cuda"):
+    """A device buffer usable as a request workspace (256-byte aligned by torch)."""
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
 def spiir_process_batch(requests, stream=None) -> None:
-    """requests: list of (bank, x, z) with torch device tensors."""
+    """requests: list of (bank, x, z) or (bank, x, z, workspace) with torch device tensors."""
     n = len(requests)
     arr = (Request * max(n, 1))()
-    for i, (bank, x, z) in enumerate(requests):
-        _validate_io(bank, x, z)
-        arr[i] = Request(bank._h, x.data_ptr(), int(x.numel()), z.data_ptr(), int(z.stride(0)))
+    for i, item in enumerate(requests):
+        arr[i] = _request(item)
     _check(load_library().spiir_process_batch(n, arr, _stream_handle(stream)), "spiir_process_batch")
 
 
@@ -238,11 +271,10 @@ class Graph:
         self._lib = lib
         n = len(requests)
         arr = (Request * max(n, 1))()
-        for i, (bank, x, z) in enumerate(requests):
-            _validate_io(bank, x, z)
-            arr[i] = Request(bank._h, x.data_ptr(), int(x.numel()), z.data_ptr(), int(z.stride(0)))
+        for i, item in enumerate(requests):
+            arr[i] = _request(item)
         # keep the tensors alive as long as the recorded pointers are used
-        self._keep = [(b, x, z) for b, x, z in requests]
+        self._keep = [tuple(item) for item in requests]
         h = C.c_void_p()
         _check(lib.spiir_graph_create(n, arr, C.byref(h)), "spiir_graph_create")
         self._h = h.value
@@ -295,15 +327,13 @@ def _validate_peaks(bank, peaks):
 
 
 def spiir_process_batch_peaks(requests, peaks, threshold: float, stream=None) -> None:
-    """requests: list of (bank, x, z or None); peaks: one peaks_empty buffer per request."""
+    """requests: list of (bank, x, z or None[, workspace]); peaks: one peaks_empty buffer per request."""
     n = len(requests)
     arr = (Request * max(n, 1))()
     pk = (C.c_void_p * max(n, 1))()
-    for i, ((bank, x, z), p) in enumerate(zip(requests, peaks)):
-        _validate_io(bank, x, z, z_optional=True)
-        _validate_peaks(bank, p)
-        arr[i] = Request(bank._h, x.data_ptr(), int(x.numel()), z.data_ptr() if z is not None else None,
-                         int(z.stride(0)) if z is not None else 0)
+    for i, (item, p) in enumerate(zip(requests, peaks)):
+        arr[i] = _request(item, z_optional=True)
+        _validate_peaks(item[0], p)
         pk[i] = p.data_ptr()
     _check(load_library().spiir_process_batch_peaks(n, arr, pk, float(threshold), _stream_handle(stream)),
            "spiir_process_batch_peaks")
@@ -341,31 +371,50 @@ class Bank:
     """One template bank bound to one input stream (owns its device memory)."""
 
     def __init__(self, tables, max_block, stream=None, precision="fp32", carry_chunk=0,
-                 filters_per_lane=0, waves_per_group=0, device=0, time_chunks=0, window_copies=0):
+                 filters_per_lane=0, waves_per_group=0, device=0, time_chunks=0, window_copies=0,
+                 workspace=WORKSPACE_OWN, _clone_of=None):
         _torch_hip_first()
         lib = load_library()
         self._lib = lib
-        hold = _DescHolder(tables, max_block, precision, carry_chunk, filters_per_lane,
-                           waves_per_group, device, time_chunks, window_copies)
-        self.n_templates = int(tables.n_filters.shape[0])
-        self.n_bands = int(tables.n_filters.shape[1])
-        self.max_block = int(max_block)
         h = C.c_void_p()
         s = _stream_handle(stream) if stream is not None else C.c_void_p(0)
-        _check(lib.spiir_create(C.byref(hold.desc), s, C.byref(h)), "spiir_create")
+        if _clone_of is not None:
+            self.n_templates, self.n_bands = _clone_of.n_templates, _clone_of.n_bands
+            self.max_block = _clone_of.max_block
+            _check(lib.spiir_clone(_clone_of._h, s, C.byref(h)), "spiir_clone")
+        else:
+            hold = _DescHolder(tables, max_block, precision, carry_chunk, filters_per_lane,
+                               waves_per_group, device, time_chunks, window_copies, workspace)
+            self.n_templates = int(tables.n_filters.shape[0])
+            self.n_bands = int(tables.n_filters.shape[1])
+            self.max_block = int(max_block)
+            _check(lib.spiir_create(C.byref(hold.desc), s, C.byref(h)), "spiir_create")
         self._h = h.value
         info = PlanInfo()
         _check(lib.spiir_bank_plan(self._h, C.byref(info)), "spiir_bank_plan")
         self.plan = {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+        self.workspace_bytes = int(self.plan["workspace_bytes"])
 
-    def process_block(self, x, z, stream=None) -> None:
+    def clone(self, stream=None) -> "Bank":
+        """spiir_clone: the same tables and plan, zero state, a stream of its own."""
+        return Bank(None, None, stream=stream, _clone_of=self)
+
+    def process_block(self, x, z, stream=None, ws=None) -> None:
+        """spiir_process_block, or with a caller workspace `ws` a one-request
+        spiir_process_batch (the same launch sequence)."""
+        if ws is not None:
+            spiir_process_batch([(self, x, z, ws)], stream)
+            return
         _validate_io(self, x, z)
         rc = self._lib.spiir_process_block(self._h, x.data_ptr(), int(x.numel()), z.data_ptr(),
                                            int(z.stride(0)), _stream_handle(stream))
         _check(rc, "spiir_process_block")
 
-    def process_peaks(self, x, z, peaks, threshold: float, stream=None) -> None:
+    def process_peaks(self, x, z, peaks, threshold: float, stream=None, ws=None) -> None:
         """process_block plus the trigger reduction into `peaks` (z may be None)."""
+        if ws is not None:
+            spiir_process_batch_peaks([(self, x, z, ws)], [peaks], threshold, stream)
+            return
         _validate_io(self, x, z, z_optional=True)
         _validate_peaks(self, peaks)
         rc = self._lib.spiir_process_peaks(self._h, x.data_ptr(), int(x.numel()),

@@ -247,3 +247,25 @@ def test_long_delays_fall_back_to_a_smaller_launch_shape():
         S.spiir_plan(tb, 4096, waves_per_group=8, window_copies=2)
     # ordinary delays keep the 8-wave default
     assert S.spiir_plan(W.config3(n_templates=8, n_blocks=1).bank, 4096, filters_per_lane=4)["lanes_per_group"] == 512
+
+
+def test_caller_workspace_leaves_the_workspace_out_of_the_footprint():
+    tb = _small_multirate(T=4, H=3)
+    own = S.spiir_plan(tb, 4096)
+    cal = S.spiir_plan(tb, 4096, workspace=S.WORKSPACE_CALLER)
+    assert own["workspace"] == S.WORKSPACE_OWN and cal["workspace"] == S.WORKSPACE_CALLER
+    assert own["workspace_bytes"] == cal["workspace_bytes"] > 0
+    assert own["workspace_bytes"] % 256 == 0
+    # the workspace is the one difference between the two footprints
+    assert 0 <= own["workspace_bytes"] - (own["footprint"] - cal["footprint"]) < 256
+    with pytest.raises(S.SpiirError) as ei:
+        S.spiir_plan(tb, 4096, workspace=2)
+    assert ei.value.code == S.SPIIR_EINVAL
+
+
+def test_clone_rejects_null():
+    lib = S.load_library()
+    out = C.c_void_p(123)
+    assert lib.spiir_clone(None, None, C.byref(out)) == S.SPIIR_EINVAL
+    assert out.value is None
+    assert lib.spiir_clone(None, None, None) == S.SPIIR_EINVAL

@@ -23,6 +23,7 @@ class VirtualOracleBackend:
         self.outputs = {}
         self.created, self.destroyed = [], []
         self.batches = []
+        self.by_bank = {}
 
     def clock(self):
         return self.t
@@ -57,6 +58,7 @@ class VirtualOracleBackend:
             assert bank.samples_done == start, "per-stream order violated"
             z = bank.process(self.x[s][start:start + n])
             self.outputs.setdefault(s, []).append((start, z))
+            self.by_bank.setdefault(id(bank), (bank, s, []))[2].append((start, z))
             cost += self.s_per_fs * bank.tables.filter_samples_per_block(n)
             rec.append((s, start, n))
         self.batches.append(rec)
@@ -147,3 +149,38 @@ def test_unadmittable_bank_raises():
     sch = SV.Scheduler(be, banks, max_block=512, hbm_budget=10)
     with pytest.raises(RuntimeError):
         sch.run(SV.make_arrivals(arr))
+
+
+def test_several_banks_per_stream():
+    """Banks share a stream (one of them twice: two banks of the same tables);
+    each filters the whole stream, and a block is done only when all have."""
+    banks, arr, xs = _setup(n_streams=2, speed=20.0)
+    units = [(0, banks[0]), (0, banks[1]), (1, banks[1]), (0, banks[0])]
+    be = VirtualOracleBackend(xs, s_per_fs=1e-8, launch_s=1e-3)
+    sch = SV.Scheduler(be, units=units, max_block=512, max_batch=3)
+    st = sch.run(SV.make_arrivals(arr))
+    assert len(be.by_bank) == 4
+    for bank, s, parts in be.by_bank.values():
+        parts = sorted(parts, key=lambda p: p[0])
+        got = np.concatenate([z for _, z in parts], axis=1)
+        ref = oracle.run_stream(bank.tables, xs[s])
+        assert got.shape == ref.shape
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    for rec in be.batches:
+        assert len(rec) <= 3
+    blocks = st.blocks
+    assert all(b.done >= b.arrival and b.remaining == 0 for b in blocks)
+    assert st.summary()["blocks"] == len(blocks)
+
+
+def test_backlog_bound_stops_an_overloaded_run():
+    banks, arr, xs = _setup(n_streams=2, dur_s=6.0)
+    be = VirtualOracleBackend(xs, s_per_fs=1e-4, launch_s=1e-3)   # far slower than real time
+    sch = SV.Scheduler(be, banks[:2], max_block=512, abort_backlog_s=1.0)
+    st = sch.run(SV.make_arrivals(arr))
+    summ = st.summary()
+    assert st.aborted and summ["aborted"]
+    assert not sch.inflight
+    assert summ["blocks"] < summ["blocks_arrived"]
+    # the run stopped about when the oldest unfinished block became 1 s old
+    assert st.wall < 6.0
