@@ -234,6 +234,24 @@ int spiir_clone(const spiir_bank* src, void* hip_stream, spiir_bank** out);
 int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
                         int64_t ldz, void* hip_stream);
 
+/*
+ * spiir_process_block_noalloc — spiir_process_block for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, results and errors,
+ * bit for bit, but the workspace of the launch sequence is a static device
+ * array of SPIIR_NOALLOC_MAX_WORKSPACE bytes that the library holds on each
+ * GPU it runs on until the process ends, and the call itself allocates
+ * nothing (no hipMalloc, hipFree or event creation; kernel timing by
+ * spiir_profile_* does not cover it).  Works for banks of either workspace
+ * mode.  A bank whose workspace (spiir_plan_info.workspace_bytes) exceeds
+ * the array returns SPIIR_ENOMEM with nothing enqueued.  Every call on one
+ * GPU shares that GPU's array: calls whose work overlaps on the device (two
+ * streams, or two host threads) race and give wrong results; calls in one
+ * stream's order are safe.
+ */
+#define SPIIR_NOALLOC_MAX_WORKSPACE (32u << 20)
+int spiir_process_block_noalloc(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
+                                int64_t ldz, void* hip_stream);
 
 /*
  * spiir_process_batch — one launch sequence over up to SPIIR_MAX_BATCH

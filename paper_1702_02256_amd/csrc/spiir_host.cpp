@@ -710,8 +710,10 @@ uint64_t layout_fingerprint(const Plan& p)
 }
 
 // peaks: the per-request trigger outputs (null for plain calls); with them a
-// request may leave z_dev null.
-int validate_batch(int32_t n_req, const spiir_request* req, spiir_peak* const* peaks = nullptr)
+// request may leave z_dev null.  static_ws: the library supplies the
+// workspace (the requests' ws_dev are not looked at).
+int validate_batch(int32_t n_req, const spiir_request* req, spiir_peak* const* peaks = nullptr,
+                   bool static_ws = false)
 {
     if (n_req < 1 || n_req > SPIIR_MAX_BATCH || !req) return SPIIR_EINVAL;
     for (int r = 0; r < n_req; ++r) {
@@ -724,7 +726,7 @@ int validate_batch(int32_t n_req, const spiir_request* req, spiir_peak* const* p
         if (peaks && !peaks[r]) return SPIIR_EINVAL;
         if (q.z_dev ? q.ldz < q.n : !peaks) return SPIIR_EINVAL;
         if (q.bank->device != req[0].bank->device) return SPIIR_EINVAL;
-        if (q.ws_dev ? ((uintptr_t)q.ws_dev & 255u) != 0 : !q.bank->zw) return SPIIR_EINVAL;
+        if (!static_ws && (q.ws_dev ? ((uintptr_t)q.ws_dev & 255u) != 0 : !q.bank->zw)) return SPIIR_EINVAL;
         for (int s = 0; s < r; ++s)
             if (req[s].bank == q.bank) return SPIIR_EORDER;
     }
@@ -1275,6 +1277,24 @@ int spiir_process_block(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c
 {
     spiir_request r{bank, x_dev, n, z_dev, ldz, nullptr};
     return spiir_process_batch(1, &r, stream);
+}
+
+int spiir_process_block_noalloc(spiir_bank* bank, const float* x_dev, int64_t n, spiir_c32* z_dev,
+                                int64_t ldz, void* stream)
+{
+    spiir_request r{bank, x_dev, n, z_dev, ldz, nullptr};
+    int rc = validate_batch(1, &r, nullptr, true);
+    if (rc) return rc;
+    if (workspace_bytes(bank->plan) > kScratchBytes) return SPIIR_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(bank->device) != hipSuccess) return SPIIR_EDEVICE;
+    if (scratch_ptr(bank->device, &r.ws_dev) != 0 || !r.ws_dev) {
+        (void)hipGetLastError();
+        return SPIIR_EDEVICE;
+    }
+    hipError_t e = wait_banks(1, &r, s);
+    if (e == hipSuccess) e = enqueue_batch(1, &r, s, false);  // no timing events: they are created on demand
+    return finish_batch(1, &r, s, e);
 }
 
 int spiir_process_batch_peaks(int32_t n_req, const spiir_request* req, spiir_peak* const* peak_dev,

@@ -25,6 +25,8 @@ constexpr int kMaxReq = SPIIR_MAX_BATCH;
 constexpr int kMaxBands = SPIIR_MAX_BANDS;
 constexpr int kMaxPiecesPerGroup = 128;
 constexpr int kSlotNone = 0xffff;
+// Size of the static workspace of spiir_process_block_noalloc.
+constexpr size_t kScratchBytes = (size_t)SPIIR_NOALLOC_MAX_WORKSPACE;
 
 // Largest workgroup of the filter kernel for F filters per lane: with 8
 // filters a lane needs more than 128 VGPRs, so at most 2 waves per SIMD.
@@ -157,5 +159,8 @@ int launch_chain(const LaunchArgs& a, int64_t nblocks, void* stream);
 int launch_fill(void* p, int64_t bytes, void* stream);
 int filter_max_lds();
 int allow_filter_lds();
+// Address of the static workspace on `device`, which must be current
+// (hipGetSymbolAddress once per device, then the kept address).
+int scratch_ptr(int device, void** out);
 
 }  // namespace spiir

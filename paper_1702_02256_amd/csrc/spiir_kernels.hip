@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <mutex>
 
 #include "spiir_internal.h"
 
@@ -1084,5 +1085,38 @@ int launch_fill(void* p, int64_t bytes, void* stream)
 }
 
 int filter_max_lds() { return 160 * 1024; }
+
+// ---------------------------------------------------------------------------
+// Static workspace of spiir_process_block_noalloc: one array per device,
+// loaded with the code object and held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address); it passes the address hipGetSymbolAddress returns
+// for the current device, taken once per device and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+int scratch_ptr(int device, void** out)
+{
+    static std::mutex mu;
+    static void* ptrs[kMaxDevices] = {};
+    *out = nullptr;
+    int cur = -1;
+    if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return (int)e;
+    if (cur != device) return (int)hipErrorInvalidDevice;  // the device must be current
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[device]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        ptrs[device] = p;
+    }
+    *out = ptrs[device];
+    return 0;
+}
 
 }  // namespace spiir

@@ -27,6 +27,7 @@ SPIIR_ENONFINITE = -5
 SPIIR_FP32 = 0
 SPIIR_FP32_COMPENSATED = 1
 MAX_BATCH = 16
+NOALLOC_MAX_WORKSPACE = 32 << 20  # bytes of the static workspace (spiir_process_block_noalloc)
 TIME_CHUNKS_AUTO = -1  # time_chunks: the library chooses the split
 WORKSPACE_OWN = 0      # spiir_create allocates the bank's workspace
 WORKSPACE_CALLER = 1   # every request brings one (spiir_request.ws_dev)
@@ -119,6 +120,7 @@ def load_library():
         "spiir_create": (C.c_int, [C.POINTER(BankDesc), vp, C.POINTER(vp)]),
         "spiir_clone": (C.c_int, [vp, vp, C.POINTER(vp)]),
         "spiir_process_block": (C.c_int, [vp, vp, i64, vp, i64, vp]),
+        "spiir_process_block_noalloc": (C.c_int, [vp, vp, i64, vp, i64, vp]),
         "spiir_process_batch": (C.c_int, [i32, C.POINTER(Request), vp]),
         "spiir_reset": (C.c_int, [vp]),
         "spiir_state_size": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
@@ -409,6 +411,13 @@ class Bank:
         rc = self._lib.spiir_process_block(self._h, x.data_ptr(), int(x.numel()), z.data_ptr(),
                                            int(z.stride(0)), _stream_handle(stream))
         _check(rc, "spiir_process_block")
+
+    def process_block_noalloc(self, x, z, stream=None) -> None:
+        """spiir_process_block_noalloc: the workspace is the library's static array."""
+        _validate_io(self, x, z)
+        rc = self._lib.spiir_process_block_noalloc(self._h, x.data_ptr(), int(x.numel()), z.data_ptr(),
+                                                   int(z.stride(0)), _stream_handle(stream))
+        _check(rc, "spiir_process_block_noalloc")
 
     def process_peaks(self, x, z, peaks, threshold: float, stream=None, ws=None) -> None:
         """process_block plus the trigger reduction into `peaks` (z may be None)."""
