@@ -430,6 +430,9 @@ def main():
     ap.add_argument("--time-chunks", type=int, default=0,
                     help="split every block in time into this many chunks (small banks); "
                          "-1: the library chooses")
+    ap.add_argument("--engine", default="valu", choices=["valu", "mfma"],
+                    help="filter engine: sample by sample on the vector units, or the matrix-core "
+                         "prototype (single-rate banks, plain FP32 sum)")
     ap.add_argument("--window-copies", type=int, default=0, choices=[0, 1, 2],
                     help="LDS copies of the filter kernel's input window (0 = library choice)")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp32_compensated"],
@@ -496,7 +499,8 @@ def main():
     bank = S.Bank(tb, block, stream=stream, precision=args.precision,
                   carry_chunk=args.carry_chunk, filters_per_lane=args.filters_per_lane,
                   waves_per_group=args.waves_per_group, time_chunks=args.time_chunks,
-                  window_copies=args.window_copies)
+                  window_copies=args.window_copies,
+                  engine=S.ENGINE_MFMA if args.engine == "mfma" else S.ENGINE_VALU)
     z = torch.zeros((T, block), dtype=torch.complex64, device="cuda")
     fs_block = tb.filter_samples_per_block(block)
     flops = W.algorithmic_flops(tb, block)
@@ -601,6 +605,7 @@ def main():
             "carry_chunk": plan["carry_chunk"],
             "time_chunks": plan["time_chunks"],
             "window_copies": plan["window_copies"],
+            "engine": args.engine,
         },
         "real_time_templates": T * block_s / (ms_step * 1e-3),
         "block_latency_ms": {"mean": float(lat.mean()), "p50": float(np.percentile(lat, 50)),

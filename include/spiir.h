@@ -138,6 +138,24 @@ enum {
  *                         many banks (one per launch sequence in flight)
  *                         instead of one per bank.  Results do not depend on
  *                         where the workspace lives.
+ *   engine                SPIIR_ENGINE_VALU (0): the filter bank runs Eq. 7
+ *                         sample by sample on the vector units.
+ *                         SPIIR_ENGINE_MFMA (1), a prototype for single-rate
+ *                         banks (H = 1) with the plain sum (SPIIR_FP32): the
+ *                         block is cut into chunks of 8 samples at absolute
+ *                         multiples of 8; the vector units carry each filter's
+ *                         state from chunk to chunk (Eq. 6 applied over a chunk,
+ *                         with the carry correction every C samples), and
+ *                         both parts of the output inside a chunk, the carried
+ *                         state times a1^(t+1) and the chunk's own inputs
+ *                         times b0 a1^(t-s) (a Toeplitz matrix), are summed
+ *                         over filters by fp16 matrix-core products with each
+ *                         operand split into a high and a low fp16 part and
+ *                         FP32 accumulation.  Requires max_block and every
+ *                         block length to be multiples of 128, time_chunks
+ *                         <= 1 (SPIIR_EINVAL otherwise), and filter states
+ *                         below 128 in magnitude (the fp16 state operand
+ *                         saturates beyond; the bank's status reports it).
  */
 typedef struct {
     int32_t n_templates;
@@ -160,6 +178,7 @@ typedef struct {
     int32_t time_chunks;
     int32_t window_copies;
     int32_t workspace;
+    int32_t engine;
 } spiir_bank_desc;
 
 #define SPIIR_MAX_BANDS 12
@@ -169,6 +188,8 @@ typedef struct {
 #define SPIIR_TIME_CHUNKS_AUTO (-1)
 #define SPIIR_WORKSPACE_OWN 0
 #define SPIIR_WORKSPACE_CALLER 1
+#define SPIIR_ENGINE_VALU 0
+#define SPIIR_ENGINE_MFMA 1
 
 /*
  * One request of a batch: the next n samples of the stream bound to `bank`.
@@ -382,6 +403,7 @@ typedef struct {
     int32_t window_copies;    /* LDS copies of the input window (1 or 2)       */
     size_t workspace_bytes;   /* device workspace one request needs            */
     int32_t workspace;        /* SPIIR_WORKSPACE_OWN or SPIIR_WORKSPACE_CALLER */
+    int32_t engine;           /* SPIIR_ENGINE_VALU or SPIIR_ENGINE_MFMA        */
 } spiir_plan_info;
 
 int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info);

@@ -61,6 +61,7 @@ struct Plan {
     int lds_filter = 0, lds_stage = 0, lds_up = 0;
     int64_t total_filters = 0, n_slots = 0, zw_elems = 0, ring_total = 0;
     int workspace = SPIIR_WORKSPACE_OWN;
+    int engine = SPIIR_ENGINE_VALU;
     int32_t n_groups = 0, n_pieces = 0;  // kept after the layout arrays are released
     std::vector<int> maxd_band, S, ring_mask;
     std::vector<int64_t> ring_off;
@@ -104,6 +105,10 @@ int validate(const spiir_bank_desc* d)
         return SPIIR_EINVAL;
     if (d->window_copies < 0 || d->window_copies > 2) return SPIIR_EINVAL;
     if (d->workspace != SPIIR_WORKSPACE_OWN && d->workspace != SPIIR_WORKSPACE_CALLER) return SPIIR_EINVAL;
+    if (d->engine != SPIIR_ENGINE_VALU && d->engine != SPIIR_ENGINE_MFMA) return SPIIR_EINVAL;
+    if (d->engine == SPIIR_ENGINE_MFMA &&
+        (H != 1 || d->precision != SPIIR_FP32 || d->max_block % kMfmaTile != 0 || d->time_chunks > 1))
+        return SPIIR_EINVAL;
     int64_t total = 0;
     for (int64_t s = 0; s < (int64_t)d->n_templates * H; ++s) {
         if (d->n_filters[s] < 0) return SPIIR_EINVAL;
@@ -548,10 +553,153 @@ int auto_time_chunks(const Plan& p)
     return P;
 }
 
+// The matrix-core engine's layout (single-rate banks): every template's
+// filters fill workgroups of kMfmaSlots slots, one template per workgroup
+// (a template with more filters gets several, each a piece of its output),
+// zero filters in the unused slots.  Each workgroup keeps the power-of-two
+// scale that brings its largest |b0 a1^j| (j < 8) near 2^14 for its fp16
+// coefficient operand.
+int make_plan_mfma(const spiir_bank_desc* d, Plan& p)
+{
+    int rc = validate(d);
+    if (rc) return rc;
+    p = Plan();
+    p.T = d->n_templates;
+    p.H = 1;
+    p.F = 1;
+    p.W = kMfmaSlots / 64;
+    p.L = kMfmaSlots;
+    p.C = d->carry_chunk ? d->carry_chunk : kDefaultC;
+    p.precision = d->precision;
+    p.workspace = d->workspace;
+    p.engine = SPIIR_ENGINE_MFMA;
+    p.max_block = d->max_block;
+    p.mb_inner = std::min(d->max_block, kInnerBlock);
+    p.td = p.tu = 1;
+    p.hu_len = 1;
+    p.P = 1;
+    p.lc[0] = p.C;
+    p.copies = 2;
+    const int T = p.T;
+    int maxd = 0;
+    int64_t total = 0;
+    for (int t = 0; t < T; ++t) total += d->n_filters[t];
+    p.total_filters = total;
+    for (int64_t l = 0; l < total; ++l) maxd = std::max(maxd, (int)d->delay[l]);
+    p.maxd_band.assign(1, maxd);
+    // window sub-block: the longest of 512, 256, 128 samples whose window fits the LDS
+    int sub = 0, X = 0;
+    for (int sb : {512, 256, 128}) {
+        sub = std::min(sb, p.mb_inner);
+        // samples per window copy: 32 mod 128, so the copies' word offsets
+        // are 16, 32 and 48 banks apart
+        X = ((maxd + sub + 65 + 127) & ~127) + 32;
+        if (4 * X * 2 + 2 * 16 * (kMfmaSlots + 4) * 4 + 4 * 16 * 17 * 4 <= kMaxLds) break;
+    }
+    if (X > kXcapMax) return SPIIR_EINVAL;
+    p.xcap = X;
+    p.S.assign(1, sub);
+    p.zstride.assign(1, (int64_t)p.mb_inner);
+    const int64_t ring = next_pow2((int64_t)p.mb_inner + std::max(maxd, 1) + 1);
+    p.ring_mask.assign(1, (int)(ring - 1));
+    p.ring_off.assign(1, 0);
+    p.ring_total = ring;
+    p.seg.assign((size_t)T, SegDesc{0, 0, 0});
+    p.band_wg0.assign(2, 0);
+    int64_t base = 0;
+    for (int t = 0; t < T; ++t) {
+        const int M = d->n_filters[t];
+        SegDesc& sg = p.seg[t];
+        sg.zoff = p.zw_elems;
+        sg.npiece = 0;
+        for (int f0 = 0; f0 < M; f0 += kMfmaSlots) {
+            WgDesc w{};
+            w.band = 0;
+            w.npiece = 1;
+            w.slot_base = p.n_slots;
+            w.meta_base = (int32_t)p.lane_meta.size();
+            w.piece_base = (int32_t)p.piece.size();
+            int wmaxd = 0;
+            double kmax = 0.0;
+            // Bank-aware order: the chunk chain of slot i reads its 8 samples at
+            // window position R - d from the copy of d's parity, whose 32-bit
+            // word falls in bank (16 (d & 1) - (d + (d & 1)) / 2) mod 64 plus a
+            // term common to all slots.  Each half-wave's 32 slots take filters
+            // of the least-used bank so far in that half-wave.
+            const int nf = std::min(kMfmaSlots, M - f0);
+            std::vector<std::vector<int>> bucket(64);
+            for (int f = nf - 1; f >= 0; --f) {
+                const int dd = d->delay[base + f0 + f];
+                bucket[((16 * (dd & 1) - (dd + (dd & 1)) / 2) % 64 + 64) % 64].push_back(f0 + f);
+            }
+            std::vector<int> order((size_t)kMfmaSlots, -1);
+            for (int hw = 0; hw < kMfmaSlots / 32; ++hw) {
+                int used[64] = {0};
+                for (int i = 0; i < 32; ++i) {
+                    int best = -1;
+                    for (int c = 0; c < 64; ++c)
+                        if (!bucket[c].empty() && (best < 0 || used[c] < used[best])) best = c;
+                    if (best < 0) break;
+                    order[hw * 32 + i] = bucket[best].back();
+                    bucket[best].pop_back();
+                    used[best]++;
+                }
+            }
+            for (int i = 0; i < kMfmaSlots; ++i) {
+                const int f = order[i];
+                if (f >= 0) {
+                    const int64_t src = base + f;
+                    p.slot_src.push_back(src);
+                    p.slot_off.push_back(d->delay[src]);
+                    wmaxd = std::max(wmaxd, (int)d->delay[src]);
+                    const double ar = d->a1[2 * src], ai = d->a1[2 * src + 1];
+                    const double am = std::sqrt(ar * ar + ai * ai);
+                    const double bm = std::hypot(d->b0[2 * src], d->b0[2 * src + 1]);
+                    kmax = std::max(kmax, bm * std::max(1.0, std::pow(am, kMfmaT - 1)));
+                } else {
+                    p.slot_src.push_back(-1);
+                    p.slot_off.push_back(0);
+                }
+                p.lane_meta.push_back(0);
+            }
+            w.maxd = wmaxd;
+            w.scale = kmax > 0.0 ? 14 - (int)std::ceil(std::log2(kmax)) : 0;
+            w.scale = std::max(-100, std::min(100, w.scale));
+            PieceDesc pc{};
+            pc.zoff = p.zw_elems;
+            pc.tmpl = t;
+            p.piece.push_back(pc);
+            p.wg.push_back(w);
+            p.zw_elems += p.zstride[0];
+            p.n_slots += kMfmaSlots;
+            sg.npiece++;
+        }
+        base += M;
+    }
+    p.band_wg0[1] = (int)p.wg.size();
+    p.lds_filter = 4 * p.xcap * 2 + 2 * 16 * (kMfmaSlots + 4) * 4 + 4 * 16 * 17 * 4;
+    p.lds_stage = ((p.td - 1) + p.mb_inner + (p.td - 1) + p.mb_inner / 2 + p.td) * 4;
+    p.lds_up = (2 * (p.hu_len + p.mb_inner / 2)) * 8 + p.tu * 4;
+    if (p.lds_filter > kMaxLds) return SPIIR_EINVAL;
+    size_t fp = 0;
+    fp += (size_t)p.n_slots * (5 * sizeof(c32) + sizeof(int32_t) + 2 * kMfmaT * sizeof(c32));
+    fp += p.wg.size() * sizeof(WgDesc) + p.piece.size() * sizeof(PieceDesc);
+    fp += p.seg.size() * sizeof(SegDesc) + p.lane_meta.size() * sizeof(int32_t);
+    fp += (size_t)p.ring_total * sizeof(float) + (size_t)(p.td + p.tu) * sizeof(float);
+    if (p.workspace == SPIIR_WORKSPACE_OWN) fp += (size_t)p.zw_elems * sizeof(c32);
+    fp += (size_t)T * p.hu_len * sizeof(c32) + (size_t)T * sizeof(int32_t) + sizeof(BankDev);
+    fp += 2 * sizeof(int64_t);
+    p.footprint = fp;
+    p.n_groups = (int32_t)p.wg.size();
+    p.n_pieces = (int32_t)p.piece.size();
+    return SPIIR_OK;
+}
+
 // The plan for a descriptor; an automatic time split plans the default (or
 // given) shape first, then the same shape split in time.
 int make_plan(const spiir_bank_desc* d, Plan& p)
 {
+    if (d && d->engine == SPIIR_ENGINE_MFMA) return make_plan_mfma(d, p);
     if (!d || d->time_chunks != SPIIR_TIME_CHUNKS_AUTO) return make_plan_fixed(d, p);
     spiir_bank_desc d1 = *d;
     d1.time_chunks = 0;
@@ -629,6 +777,7 @@ struct spiir_bank {
     int32_t* flags = nullptr;
     int64_t* clock = nullptr;
     c32 *al = nullptr, *uend = nullptr, *schain = nullptr, *ys0 = nullptr;
+    c32 *kc = nullptr, *pw = nullptr;  // matrix-core engine tables
     BankDev* bd = nullptr;
 };
 
@@ -646,7 +795,8 @@ void free_bank(spiir_bank* b)
 {
     if (!b) return;
     void* ptrs[] = {b->a,     b->b,     b->dc, b->y,  b->ys, b->off, b->wg,     b->piece, b->seg,
-                    b->lane_meta, b->rings, b->hd, b->hu, b->zw, b->uphist, b->flags, b->clock, b->al, b->uend, b->schain, b->ys0, b->bd};
+                    b->lane_meta, b->rings, b->hd, b->hu, b->zw, b->uphist, b->flags, b->clock, b->al, b->uend, b->schain, b->ys0,
+                    b->kc, b->pw, b->bd};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (b->ev) (void)hipEventDestroy(b->ev);
@@ -706,6 +856,7 @@ uint64_t layout_fingerprint(const Plan& p)
     mix(p.band_wg0.data(), p.band_wg0.size() * sizeof(int));
     mix(p.ring_mask.data(), p.ring_mask.size() * sizeof(int));
     mix(&p.hu_len, sizeof(p.hu_len));
+    mix(&p.engine, sizeof(p.engine));
     return h;
 }
 
@@ -722,6 +873,7 @@ int validate_batch(int32_t n_req, const spiir_request* req, spiir_peak* const* p
         if (q.bank->poisoned) return SPIIR_EDEVICE;
         const Plan& p = q.bank->plan;
         if (q.n <= 0 || q.n > p.max_block || q.n % (1 << (p.H - 1)) != 0) return SPIIR_EINVAL;
+        if (p.engine == SPIIR_ENGINE_MFMA && q.n % kMfmaTile != 0) return SPIIR_EINVAL;
         if (!q.x_dev) return SPIIR_EINVAL;
         if (peaks && !peaks[r]) return SPIIR_EINVAL;
         if (q.z_dev ? q.ldz < q.n : !peaks) return SPIIR_EINVAL;
@@ -783,15 +935,17 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
         // one filter launch per launch shape (filters per lane, lanes, precision)
         // among the requests, in order of first appearance
         struct Shape {
-            int F, L, prec;
+            int F, L, prec, engine;
         };
         Shape shape_buf[kMaxReq];
         int nshape = 0;
         auto shape_of = [&](int k) {
             const Plan& p = req[rmap[k]].bank->plan;
-            return Shape{p.F, p.L, p.precision};
+            return Shape{p.F, p.L, p.precision, p.engine};
         };
-        auto same = [](const Shape& a, const Shape& b) { return a.F == b.F && a.L == b.L && a.prec == b.prec; };
+        auto same = [](const Shape& a, const Shape& b) {
+            return a.F == b.F && a.L == b.L && a.prec == b.prec && a.engine == b.engine;
+        };
         for (int k = 0; k < A.nreq; ++k) {
             bool seen = false;
             for (int i = 0; i < nshape; ++i) seen |= same(shape_buf[i], shape_of(k));
@@ -875,7 +1029,9 @@ hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s,
             LaunchArgs X = A;
             const int n0 = segments(X, false, sh);
             if (e == hipSuccess && n0 > 0)
-                e = (hipError_t)launch_filter(sh.F, sh.prec, X, n0, sh.L, shape_lds(sh, false), s);
+                e = (hipError_t)(sh.engine == SPIIR_ENGINE_MFMA
+                                     ? launch_filter_mfma(X, n0, shape_lds(sh, false), s)
+                                     : launch_filter(sh.F, sh.prec, X, n0, sh.L, shape_lds(sh, false), s));
         }
         mark(2);
         if (e == hipSuccess) e = (hipError_t)launch_upadd(A, ntm, lds_u, s);
@@ -948,6 +1104,7 @@ static void fill_plan_info(const Plan& p, spiir_plan_info* info)
     info->window_copies = p.copies;
     info->workspace_bytes = workspace_bytes(p);
     info->workspace = p.workspace;
+    info->engine = p.engine;
 }
 
 int spiir_plan(const spiir_bank_desc* desc, spiir_plan_info* info)
@@ -982,6 +1139,8 @@ int spiir_footprint(const spiir_bank_desc* desc, size_t* bytes)
     return SPIIR_OK;
 }
 
+static c64 cmul_h(c64 u, c64 v) { return c64{u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x}; }
+
 // Device arrays of a bank, sized from its plan (which may already have
 // released its layout arrays: only counts are read here).
 static bool alloc_bank(spiir_bank* b)
@@ -1010,6 +1169,10 @@ static bool alloc_bank(spiir_bank* b)
         ok &= dalloc(&b->uend, (size_t)(p.P + 1) * p.n_slots) == hipSuccess;
         ok &= dalloc(&b->schain, (size_t)(p.P + 1) * p.n_slots) == hipSuccess;
         ok &= dalloc(&b->ys0, p.n_slots) == hipSuccess;
+    }
+    if (p.engine == SPIIR_ENGINE_MFMA) {
+        ok &= dalloc(&b->kc, (size_t)p.n_slots * kMfmaT) == hipSuccess;
+        ok &= dalloc(&b->pw, (size_t)p.n_slots * kMfmaT) == hipSuccess;
     }
     ok &= dalloc(&b->bd, 1) == hipSuccess;
     ok &= hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) == hipSuccess;
@@ -1067,6 +1230,9 @@ static BankDev bank_dev(const spiir_bank* b)
     bd.uend = b->uend;
     bd.schain = b->schain;
     bd.ys0 = b->ys0;
+    bd.engine = p.engine;
+    bd.kc = b->kc;
+    bd.pw = b->pw;
     return bd;
 }
 
@@ -1185,8 +1351,47 @@ int spiir_create(const spiir_bank_desc* desc, void* stream, spiir_bank** out)
     up(b->hd, hd.data(), sizeof(float) * p.td);
     up(b->hu, hu.data(), sizeof(float) * p.tu);
     up(b->bd, &bd, sizeof(BankDev));
-    if (e == hipSuccess)
+    // matrix-core engine: its tables are FP64 powers rounded once, on the host
+    std::vector<c32> ma, mz, mdc, mkc, mpw;
+    if (p.engine == SPIIR_ENGINE_MFMA) {
+        try {
+            ma.resize((size_t)p.n_slots);
+            mz.assign((size_t)p.n_slots, c32{0.0f, 0.0f});
+            mdc.resize((size_t)p.n_slots);
+            mkc.resize((size_t)p.n_slots * kMfmaT);
+            mpw.resize((size_t)p.n_slots * kMfmaT);
+        } catch (const std::bad_alloc&) {
+            e = hipErrorOutOfMemory;
+        }
+        for (int64_t g = 0; g < p.n_slots && e == hipSuccess; ++g) {
+            const c64 a = ha[g], bb = hb[g];
+            c64 pw{1.0, 0.0};
+            for (int j = 0; j < kMfmaT; ++j) {
+                const c64 k = cmul_h(bb, pw);
+                mkc[g * kMfmaT + j] = c32{(float)k.x, (float)k.y};
+                pw = cmul_h(pw, a);
+                mpw[g * kMfmaT + j] = c32{(float)pw.x, (float)pw.y};
+            }
+            // pw = a^8: the chunk-to-chunk factor, and the correction of its FP32
+            // rounding over C samples, a^C - fl32(a^8)^(C/8), both in FP64
+            const c32 a8{(float)pw.x, (float)pw.y};
+            c64 exact{1.0, 0.0}, rounded{1.0, 0.0};
+            const c64 a8r{a8.x, a8.y};
+            for (int c = 0; c < p.C / kMfmaT; ++c) {
+                exact = cmul_h(exact, pw);
+                rounded = cmul_h(rounded, a8r);
+            }
+            ma[g] = a8;
+            mdc[g] = c32{(float)(exact.x - rounded.x), (float)(exact.y - rounded.y)};
+        }
+        up(b->a, ma.data(), sizeof(c32) * p.n_slots);
+        up(b->b, mz.data(), sizeof(c32) * p.n_slots);
+        up(b->dc, mdc.data(), sizeof(c32) * p.n_slots);
+        up(b->kc, mkc.data(), sizeof(c32) * p.n_slots * kMfmaT);
+        up(b->pw, mpw.data(), sizeof(c32) * p.n_slots * kMfmaT);
+    } else if (e == hipSuccess) {
         e = (hipError_t)launch_prep(da, db, p.n_slots, p.C, b->a, b->b, b->dc, dlc, b->al, s);
+    }
     if (e == hipSuccess) e = (hipError_t)zero_state(b, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(da);
@@ -1244,6 +1449,10 @@ int spiir_clone(const spiir_bank* src, void* stream, spiir_bank** out)
     dd(b->hd, src->hd, sizeof(float) * p.td);
     dd(b->hu, src->hu, sizeof(float) * p.tu);
     if (p.P > 1) dd(b->al, src->al, sizeof(c32) * p.n_slots);
+    if (p.engine == SPIIR_ENGINE_MFMA) {
+        dd(b->kc, src->kc, sizeof(c32) * p.n_slots * kMfmaT);
+        dd(b->pw, src->pw, sizeof(c32) * p.n_slots * kMfmaT);
+    }
     if (e == hipSuccess && (e = hipMemcpyAsync(b->bd, &bd, sizeof(BankDev), hipMemcpyHostToDevice, s)) == hipSuccess)
         e = (hipError_t)zero_state(b, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

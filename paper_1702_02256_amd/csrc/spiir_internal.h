@@ -25,6 +25,11 @@ constexpr int kMaxReq = SPIIR_MAX_BATCH;
 constexpr int kMaxBands = SPIIR_MAX_BANDS;
 constexpr int kMaxPiecesPerGroup = 128;
 constexpr int kSlotNone = 0xffff;
+// Matrix-core engine: samples per chunk, filters per workgroup (one lane
+// each in the chunk chain), samples per output tile (16 chunks).
+constexpr int kMfmaT = 8;
+constexpr int kMfmaSlots = 256;
+constexpr int kMfmaTile = 128;
 // Size of the static workspace of spiir_process_block_noalloc.
 constexpr size_t kScratchBytes = (size_t)SPIIR_NOALLOC_MAX_WORKSPACE;
 
@@ -53,6 +58,8 @@ struct WgDesc {
     int64_t slot_base;   // filter slot (f, lane) lives at slot_base + f*L + lane
     int32_t meta_base;   // L lane-meta words: (piece << 16) | run slot (or kSlotNone)
     int32_t piece_base;  // first PieceDesc
+    int32_t scale;       // matrix-core engine: log2 of the fp16 scale of its b0 a1^j
+    int32_t pad;
 };
 
 // A contiguous lane range of one (template, band) segment inside a workgroup.
@@ -116,6 +123,12 @@ struct BankDev {
     c32* uend;                      // [P+1][n_slots] chunk end states from zero start
     c32* schain;                    // [P+1][n_slots] chained chunk start states
     c32* ys0;                       // [n_slots] pending carry correction entering the block
+    // Matrix-core engine (engine == SPIIR_ENGINE_MFMA): `a` holds fl32(a1^8),
+    // `dc` the chunk-chain carry correction a1^C - fl32(a1^8)^(C/8), and
+    //   kc[8*slot + j] = b0 a1^j, pw[8*slot + t] = a1^(t+1), j, t < 8.
+    int32_t engine;
+    const c32* kc;
+    const c32* pw;
 };
 
 struct ReqArg {
@@ -150,6 +163,7 @@ static_assert(sizeof(LaunchArgs) <= 4096, "launch arguments exceed the kernel ar
 int launch_stage(const LaunchArgs& a, int lds_bytes, void* stream);
 int launch_filter(int F, int precision, const LaunchArgs& a, int nblocks, int L, int lds_bytes,
                   void* stream);
+int launch_filter_mfma(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream);
 int launch_upadd(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream);
 int launch_prep(const c64* a, const c64* b, int64_t n, int C, c32* fa, c32* fb, c32* fdc,
                 const int32_t* slot_lc, c32* fal, void* stream);

@@ -591,6 +591,273 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
 }
 
 // ---------------------------------------------------------------------------
+// The filter bank on the matrix cores (single-rate banks; engine MFMA).
+//
+// Over a chunk of T = 8 samples starting at an absolute multiple of 8 (c is
+// the chunk, Y_l[c] filter l's state before it), Eq. 6 applied to Eq. 7 gives
+//   y_l[8c + t] = a_l^(t+1) Y_l[c] + sum_{s<=t} b_l a_l^(t-s) x[8c + s - d_l],
+// so the sum over filters (Eq. 8) of one chunk is two matrix products with
+// rows (t, re/im): a 16 x (2 per filter) block of powers a_l^(t+1) times the
+// chunk states, and a 16 x (8 per filter) lower-triangular Toeplitz block of
+// b_l a_l^(t-s) times the chunk's delayed inputs.  Both go through
+// v_mfma_f32_16x16x32_f16 over 16 chunks at a time, each operand split into
+// an fp16 high part and the fp16 rounding of the remainder (hi*hi + hi*lo +
+// lo*hi, FP32 accumulation; the coefficients scaled by a power of two that
+// keeps them in the fp16 range).  The vector units carry the states from
+// chunk to chunk, Y[c+1] = a^8 Y[c] + sum_s b a^(7-s) x[8c + s - d], with the
+// carry correction of the per-sample form applied every C/8 chunks.
+//
+// One workgroup of 256 threads per (template, up to 256 of its filters);
+// thread i runs the chunk chain of filter i, wave w owns filters
+// 64w .. 64w+63 in the products.  The input window is staged once per
+// sub-block already split, as fp16 high and low parts, each held twice (the
+// second copy one sample ahead) so that 8 samples from any position are four
+// aligned 32-bit reads.  Per 128-sample tile: the chain stores the 16 chunk
+// states (scaled, split) in LDS; each wave multiplies its filters' blocks;
+// the four waves' partial sums are added in LDS and written as the piece's
+// band output.
+// LDS: Xh0 Xh1 Xl0 Xl1 [xcap] fp16 each | Yh [16][kMfmaYRow] half2 | Yl [same] | zp [4][16][kMfmaZRow] f32
+// (rows padded so that the 16 chunks of a column read, and the 4 row groups
+// of a partial-sum store, fall in different banks)
+// ---------------------------------------------------------------------------
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kMfmaK2 = 16;    // Toeplitz K-blocks per wave (4 filters x 8 samples each)
+constexpr int kMfmaK1 = 4;     // state K-blocks per wave (16 filters x re/im each)
+constexpr int kMfmaSP = 14;    // log2 scale of the powers a1^(t+1)
+constexpr int kMfmaSY = 8;     // log2 scale of the chunk states
+constexpr int kMfmaYRow = kMfmaSlots + 4;  // words per chunk row of the state tile
+constexpr int kMfmaZRow = 17;              // words per row of a wave's partial sums
+
+__device__ __forceinline__ void split16(float v, _Float16& hi, _Float16& lo)
+{
+    hi = (_Float16)v;
+    lo = (_Float16)(v - (float)hi);
+}
+
+__device__ __forceinline__ uint32_t pack_h2(_Float16 a, _Float16 b)
+{
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+// 8 fp16 values from position p of a window held twice (X1 one ahead of X0):
+// four aligned 32-bit reads
+__device__ __forceinline__ half8_t load8h(const _Float16* X0, const _Float16* X1, int p)
+{
+    const uint32_t* w = reinterpret_cast<const uint32_t*>((p & 1) ? X1 + p - 1 : X0 + p);
+    const uint4 v = make_uint4(w[0], w[1], w[2], w[3]);
+    return __builtin_bit_cast(half8_t, v);
+}
+
+__global__ void __launch_bounds__(kMfmaSlots, 2) k_filter_mfma(LaunchArgs args)
+{
+    extern __shared__ float sm[];
+    const int bid = blockIdx.x;
+    int lo = 0, hi = args.nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (args.cum[mid] <= bid) lo = mid;
+        else hi = mid;
+    }
+    const ReqArg& q = args.req[args.seg_req[lo]];
+    CBankDev* bd = cmem(q.bd);
+    const WgDesc wg = cmem(bd->wg)[bd->band_wg0[0] + (bid - args.cum[lo])];
+    const PieceDesc pd = cmem(bd->piece)[wg.piece_base];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int n = q.n;
+    const int64_t s0 = cmem(bd->clock)[0];
+    const int xcap = bd->xcap;  // a multiple of 32 samples
+    _Float16* Xh0 = reinterpret_cast<_Float16*>(sm);
+    _Float16* Xh1 = Xh0 + xcap;
+    _Float16* Xl0 = Xh1 + xcap;
+    _Float16* Xl1 = Xl0 + xcap;
+    uint32_t* Yh = reinterpret_cast<uint32_t*>(Xl1 + xcap);
+    uint32_t* Yl = Yh + 16 * kMfmaYRow;
+    float* zp = reinterpret_cast<float*>(Yl + 16 * kMfmaYRow);
+
+    // chunk chain of filter slot tid
+    const int64_t g = wg.slot_base + tid;
+    const SPIIR_AS_CONST c32* kc = cmem(bd->kc);
+    const SPIIR_AS_CONST c32* pw = cmem(bd->pw);
+    c32 Y = gmem(bd->y)[g], u = gmem(bd->ys)[g];
+    const c32 a8 = cmem(bd->a)[g], dc = cmem(bd->dc)[g];
+    const int dA = cmem(bd->off)[g];
+    float wr[kMfmaT], wi[kMfmaT];  // b a^(7-s): weight of sample s in the chunk's end state
+#pragma unroll
+    for (int s = 0; s < kMfmaT; ++s) {
+        const c32 k = kc[g * kMfmaT + (kMfmaT - 1 - s)];
+        wr[s] = k.x;
+        wi[s] = k.y;
+    }
+    const int64_t cmask = bd->C - 1;
+
+    // matrix operands of this wave: row r = (t, part), column group g4
+    const int r = lane & 15, g4 = lane >> 4, t = r & 7, part = r >> 3, col = lane & 15;
+    const float sA = ldexpf(1.0f, wg.scale);
+    half8_t Ah[kMfmaK2], Al[kMfmaK2], Ph[kMfmaK1], Pl[kMfmaK1];
+    int dB[kMfmaK2];
+#pragma unroll
+    for (int kb = 0; kb < kMfmaK2; ++kb) {
+        const int64_t gf = wg.slot_base + wave * 64 + 4 * kb + g4;
+#pragma unroll
+        for (int s = 0; s < kMfmaT; ++s) {
+            const c32 k = kc[gf * kMfmaT + ((t - s) & (kMfmaT - 1))];
+            const float v = s <= t ? (part ? k.y : k.x) * sA : 0.0f;
+            _Float16 h, l;
+            split16(v, h, l);
+            Ah[kb][s] = h;
+            Al[kb][s] = l;
+        }
+        dB[kb] = cmem(bd->off)[gf];
+    }
+#pragma unroll
+    for (int kb = 0; kb < kMfmaK1; ++kb) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t gf = wg.slot_base + wave * 64 + 16 * kb + 4 * g4 + (j >> 1);
+            const c32 p = pw[gf * kMfmaT + t];
+            // row (t, re): Re p Re Y - Im p Im Y;  row (t, im): Im p Re Y + Re p Im Y
+            const float v = part == 0 ? ((j & 1) ? -p.y : p.x) : ((j & 1) ? p.x : p.y);
+            _Float16 h, l;
+            split16(ldexpf(v, kMfmaSP), h, l);
+            Ph[kb][j] = h;
+            Pl[kb][j] = l;
+        }
+    }
+    const float unA = ldexpf(1.0f, -wg.scale), unP = ldexpf(1.0f, -(kMfmaSP + kMfmaSY));
+    const float sY = ldexpf(1.0f, kMfmaSY);
+
+    const int S = bd->S[0];
+    const SPIIR_AS_CONST float* ring = cmem(bd->rings) + bd->ring_off[0];
+    const int64_t mk = bd->ring_mask[0];
+    SPIIR_AS_GLOBAL float* zout = reinterpret_cast<SPIIR_AS_GLOBAL float*>(gmem(q.zw) + pd.zoff);
+    bool sat = false;
+    for (int kb0 = 0; kb0 < n; kb0 += S) {
+        const int sub = min(S, n - kb0);
+        const int64_t origin = ((s0 + kb0 - wg.maxd - 1) >> 6) << 6;
+        const int wn = (int)(s0 + kb0 + sub - origin);
+        __syncthreads();
+        // thread j writes word j of each copy: samples (2j, 2j+1) of X*0 and
+        // (2j+1, 2j+2) of X*1, from x[origin + 2j .. origin + 2j + 2]
+        uint32_t* Wh0 = reinterpret_cast<uint32_t*>(Xh0);
+        uint32_t* Wh1 = reinterpret_cast<uint32_t*>(Xh1);
+        uint32_t* Wl0 = reinterpret_cast<uint32_t*>(Xl0);
+        uint32_t* Wl1 = reinterpret_cast<uint32_t*>(Xl1);
+        for (int j = tid; 2 * j < wn; j += kMfmaSlots) {
+            const int i = 2 * j;
+            const float v0 = ring[(origin + i) & mk];
+            const float v1 = i + 1 <= wn ? ring[(origin + i + 1) & mk] : 0.0f;
+            const float v2 = i + 2 <= wn ? ring[(origin + i + 2) & mk] : 0.0f;
+            _Float16 h0, l0, h1, l1, h2, l2;
+            split16(v0, h0, l0);
+            split16(v1, h1, l1);
+            split16(v2, h2, l2);
+            Wh0[j] = pack_h2(h0, h1);
+            Wl0[j] = pack_h2(l0, l1);
+            Wh1[j] = pack_h2(h1, h2);
+            Wl1[j] = pack_h2(l1, l2);
+        }
+        __syncthreads();
+        for (int k0 = kb0; k0 < kb0 + sub; k0 += kMfmaTile) {
+            const int rel0 = (int)(s0 + k0 - origin);  // window position of the tile's first sample
+            // chunk chain, four chunks at a time: their input sums first
+            // (independent), then the states in order, each stored (scaled,
+            // split) before its chunk
+#pragma unroll 1
+            for (int c4 = 0; c4 < 16; c4 += 4) {
+            float er[4], ei[4];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const int p = rel0 + kMfmaT * (c4 + cc) - dA;
+                const half8_t xh = load8h(Xh0, Xh1, p);
+                const half8_t xl = load8h(Xl0, Xl1, p);
+                float ar = 0.0f, ai = 0.0f, br = 0.0f, bi = 0.0f;
+#pragma unroll
+                for (int s = 0; s < kMfmaT; ++s) {
+                    const float x = (float)xh[s] + (float)xl[s];
+                    if (s & 1) {
+                        br = fmaf(wr[s], x, br);
+                        bi = fmaf(wi[s], x, bi);
+                    } else {
+                        ar = fmaf(wr[s], x, ar);
+                        ai = fmaf(wi[s], x, ai);
+                    }
+                }
+                er[cc] = ar + br;
+                ei[cc] = ai + bi;
+            }
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const int c = c4 + cc;
+                _Float16 hr, lr, hi_, li;
+                const float yr = Y.x * sY, yi = Y.y * sY;
+                sat |= !(fabsf(yr) < 32768.0f && fabsf(yi) < 32768.0f);
+                split16(yr, hr, lr);
+                split16(yi, hi_, li);
+                Yh[c * kMfmaYRow + tid] = pack_h2(hr, hi_);
+                Yl[c * kMfmaYRow + tid] = pack_h2(lr, li);
+                const float nr = fmaf(a8.x, Y.x, fmaf(-a8.y, Y.y, er[cc]));
+                const float ni = fmaf(a8.x, Y.y, fmaf(a8.y, Y.x, ei[cc]));
+                Y = c32{nr, ni};
+                if (((s0 + k0 + kMfmaT * (c + 1)) & cmask) == 0) {
+                    Y.x += u.x;
+                    Y.y += u.y;
+                    u = c32{fmaf(dc.x, Y.x, -dc.y * Y.y), fmaf(dc.x, Y.y, dc.y * Y.x)};
+                }
+            }
+            }
+            __syncthreads();
+            // the wave's filters: Toeplitz input part and state part of 16 chunks,
+            // in independent accumulators
+            f32x4_t D2[4], D1[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) D2[i] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < 2; ++i) D1[i] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kb = 0; kb < kMfmaK2; ++kb) {
+                const int p = rel0 + kMfmaT * col - dB[kb];
+                const half8_t bh = load8h(Xh0, Xh1, p);
+                const half8_t bl = load8h(Xl0, Xl1, p);
+                f32x4_t& D = D2[kb & 3];
+                D = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah[kb], bh, D, 0, 0, 0);
+                D = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah[kb], bl, D, 0, 0, 0);
+                D = __builtin_amdgcn_mfma_f32_16x16x32_f16(Al[kb], bh, D, 0, 0, 0);
+            }
+#pragma unroll
+            for (int kb = 0; kb < kMfmaK1; ++kb) {
+                const int f0 = wave * 64 + 16 * kb + 4 * g4;
+                const uint4 hv = *reinterpret_cast<const uint4*>(Yh + col * kMfmaYRow + f0);
+                const uint4 lv = *reinterpret_cast<const uint4*>(Yl + col * kMfmaYRow + f0);
+                const half8_t bh = __builtin_bit_cast(half8_t, hv);
+                const half8_t bl = __builtin_bit_cast(half8_t, lv);
+                f32x4_t& D = D1[kb & 1];
+                D = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ph[kb], bh, D, 0, 0, 0);
+                D = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ph[kb], bl, D, 0, 0, 0);
+                D = __builtin_amdgcn_mfma_f32_16x16x32_f16(Pl[kb], bh, D, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v2 = (D2[0][i] + D2[1][i]) + (D2[2][i] + D2[3][i]);
+                zp[(wave * 16 + 4 * g4 + i) * kMfmaZRow + col] = fmaf(v2, unA, (D1[0][i] + D1[1][i]) * unP);
+            }
+            __syncthreads();
+            // sum of the four waves' partials: element (row, chunk) = (tid >> 4, tid & 15)
+            {
+                const int row = tid >> 4, ch = tid & 15;
+                const float* zr = zp + row * kMfmaZRow + ch;
+                const float v = (zr[0] + zr[16 * kMfmaZRow]) + (zr[32 * kMfmaZRow] + zr[48 * kMfmaZRow]);
+                zout[2 * (int64_t)(k0 + kMfmaT * ch + (row & 7)) + (row >> 3)] = v;
+            }
+        }
+    }
+    gmem(bd->y)[g] = Y;
+    gmem(bd->ys)[g] = u;
+    if (sat || !(isfinite(Y.x) && isfinite(Y.y))) atomicOr(&bd->flags[pd.tmpl], 1);
+}
+
+// ---------------------------------------------------------------------------
 // Upsample-and-add chain, one workgroup of kUpThreads per (request, template).
 // The piece sums of bands 1.. are fetched into registers first (one burst of
 // independent loads), band 0's once the lowest band is in LDS, so they arrive
@@ -1009,6 +1276,9 @@ int allow_filter_lds()
 {
     int e = (int)hipFuncSetAttribute((const void*)k_upadd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      filter_max_lds());
+    if (!e)
+        e = (int)hipFuncSetAttribute((const void*)k_filter_mfma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     filter_max_lds());
     if (!e) e = allow_lds_t<1, false>();
     if (!e) e = allow_lds_t<1, true>();
     if (!e) e = allow_lds_t<2, false>();
@@ -1054,6 +1324,12 @@ int launch_filter_local(int F, int precision, const LaunchArgs& a, int nblocks, 
 {
     (void)precision;
     return launch_filter_any<true>(F, SPIIR_FP32, a, nblocks, L, lds_bytes, (hipStream_t)stream);
+}
+
+int launch_filter_mfma(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream)
+{
+    hipLaunchKernelGGL(k_filter_mfma, dim3(nblocks), dim3(kMfmaSlots), lds_bytes, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
 }
 
 int launch_upadd(const LaunchArgs& a, int nblocks, int lds_bytes, void* stream)

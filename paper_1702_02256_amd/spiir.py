@@ -15,7 +15,8 @@ import re
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libspiir.so")
+# SPIIR_LIB_PATH selects another build of the same library (same ABI).
+LIB_PATH = os.environ.get("SPIIR_LIB_PATH") or os.path.join(_PKG, "libspiir.so")
 HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "spiir.h")
 
 SPIIR_OK = 0
@@ -31,6 +32,8 @@ NOALLOC_MAX_WORKSPACE = 32 << 20  # bytes of the static workspace (spiir_process
 TIME_CHUNKS_AUTO = -1  # time_chunks: the library chooses the split
 WORKSPACE_OWN = 0      # spiir_create allocates the bank's workspace
 WORKSPACE_CALLER = 1   # every request brings one (spiir_request.ws_dev)
+ENGINE_VALU = 0        # the filter bank sample by sample on the vector units
+ENGINE_MFMA = 1        # prototype: single-rate banks through the matrix cores
 
 _PRECISION = {"fp32": SPIIR_FP32, "fp32_compensated": SPIIR_FP32_COMPENSATED,
               "compensated": SPIIR_FP32_COMPENSATED}
@@ -58,6 +61,7 @@ class BankDesc(C.Structure):
         ("time_chunks", C.c_int32),
         ("window_copies", C.c_int32),
         ("workspace", C.c_int32),
+        ("engine", C.c_int32),
     ]
 
 
@@ -87,6 +91,7 @@ class PlanInfo(C.Structure):
         ("window_copies", C.c_int32),
         ("workspace_bytes", C.c_size_t),
         ("workspace", C.c_int32),
+        ("engine", C.c_int32),
     ]
 
 
@@ -177,7 +182,8 @@ class _DescHolder:
     """A BankDesc plus the numpy arrays its pointers refer to."""
 
     def __init__(self, tables, max_block, precision="fp32", carry_chunk=0, filters_per_lane=0,
-                 waves_per_group=0, device=0, time_chunks=0, window_copies=0, workspace=WORKSPACE_OWN):
+                 waves_per_group=0, device=0, time_chunks=0, window_copies=0, workspace=WORKSPACE_OWN,
+                 engine=ENGINE_VALU):
         self.nf = np.ascontiguousarray(tables.n_filters.reshape(-1), dtype=np.int32)
         self.a1 = np.ascontiguousarray(np.asarray(tables.a1, np.complex128)).view(np.float64)
         self.b0 = np.ascontiguousarray(np.asarray(tables.b0, np.complex128)).view(np.float64)
@@ -197,7 +203,7 @@ class _DescHolder:
             max_block=int(max_block), precision=prec, carry_chunk=int(carry_chunk),
             filters_per_lane=int(filters_per_lane), waves_per_group=int(waves_per_group),
             device=int(device), time_chunks=int(time_chunks), window_copies=int(window_copies),
-            workspace=int(workspace))
+            workspace=int(workspace), engine=int(engine))
 
 
 # ---------------------------------------------------------------- C-named functions
@@ -374,7 +380,7 @@ class Bank:
 
     def __init__(self, tables, max_block, stream=None, precision="fp32", carry_chunk=0,
                  filters_per_lane=0, waves_per_group=0, device=0, time_chunks=0, window_copies=0,
-                 workspace=WORKSPACE_OWN, _clone_of=None):
+                 workspace=WORKSPACE_OWN, engine=ENGINE_VALU, _clone_of=None):
         _torch_hip_first()
         lib = load_library()
         self._lib = lib
@@ -386,7 +392,7 @@ class Bank:
             _check(lib.spiir_clone(_clone_of._h, s, C.byref(h)), "spiir_clone")
         else:
             hold = _DescHolder(tables, max_block, precision, carry_chunk, filters_per_lane,
-                               waves_per_group, device, time_chunks, window_copies, workspace)
+                               waves_per_group, device, time_chunks, window_copies, workspace, engine)
             self.n_templates = int(tables.n_filters.shape[0])
             self.n_bands = int(tables.n_filters.shape[1])
             self.max_block = int(max_block)

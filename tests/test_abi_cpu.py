@@ -269,3 +269,21 @@ def test_clone_rejects_null():
     assert lib.spiir_clone(None, None, C.byref(out)) == S.SPIIR_EINVAL
     assert out.value is None
     assert lib.spiir_clone(None, None, None) == S.SPIIR_EINVAL
+
+
+def test_matrix_core_engine_descriptor_rules():
+    wl = W.config2(n_templates=3, n_blocks=1)
+    p = S.spiir_plan(wl.bank, 2048, engine=S.ENGINE_MFMA)
+    assert p["engine"] == S.ENGINE_MFMA
+    # one template per 256-slot workgroup: 512 filters -> 2 workgroups each
+    assert p["n_groups"] == 6 and p["n_pieces"] == 6 and p["filter_slots"] == 6 * 256
+    for kw in ({"precision": "fp32_compensated"}, {"time_chunks": 4}):
+        with pytest.raises(S.SpiirError) as ei:
+            S.spiir_plan(wl.bank, 2048, engine=S.ENGINE_MFMA, **kw)
+        assert ei.value.code == S.SPIIR_EINVAL
+    with pytest.raises(S.SpiirError):
+        S.spiir_plan(wl.bank, 2000, engine=S.ENGINE_MFMA)       # max_block % 128
+    with pytest.raises(S.SpiirError):
+        S.spiir_plan(_small_multirate(), 1024, engine=S.ENGINE_MFMA)  # more than one band
+    with pytest.raises(S.SpiirError):
+        S.spiir_plan(wl.bank, 2048, engine=2)
