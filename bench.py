@@ -194,7 +194,7 @@ def serving_bench(args, S, W, torch, np):
 
     1. Saturated step (``value``, roofline): one 1 s block of every stream per
        batch, back to back, inputs resident in HBM.
-    2. Real-time capacity: k copies of the three banks resident at once
+    2. Real-time capacity: k copies of the stream banks resident at once
        (16384 k templates; copies made with spiir_clone, each with its own
        tables and state), blocks of 0.125-1 s arriving by a Poisson process at
        real time on every stream, served by the continuous-batching scheduler
@@ -207,12 +207,21 @@ def serving_bench(args, S, W, torch, np):
     n_streams, rate = 3, 4096
     total_t = args.templates or 16384
     tables = W.serving_banks(n_templates=total_t, n_streams=n_streams)
+    streams_of = list(range(n_streams))
+    if args.serve_split > 1:
+        # each stream's templates in serve_split banks of about equal size
+        split, streams_of = [], []
+        for s, t in enumerate(tables):
+            for part in np.array_split(np.arange(t.n_templates), args.serve_split):
+                split.append(t.subset(part))
+                streams_of.append(s)
+        tables = split
     max_block = 8192
     prec = args.precision
     stream = torch.cuda.Stream()
     base = [S.Bank(t, max_block, stream=stream, precision=prec, workspace=S.WORKSPACE_CALLER)
             for t in tables]
-    print(f"serving: {total_t} templates in {n_streams} banks created", file=sys.stderr, flush=True)
+    print(f"serving: {total_t} templates in {len(base)} banks created", file=sys.stderr, flush=True)
     ws_bytes = max(b.workspace_bytes for b in base)
 
     # ---- 1. saturated closed loop: one 1 s block of every stream per batch
@@ -220,14 +229,16 @@ def serving_bench(args, S, W, torch, np):
     blk = rate
     xs_sat = [W.noise_stream(2000 + s, blk * (K + Wm)) for s in range(n_streams)]
     xt = [torch.from_numpy(x.astype(np.float32)).cuda() for x in xs_sat]
-    wss = [S.workspace_empty(ws_bytes) for _ in range(n_streams)]
+    wss = [S.workspace_empty(ws_bytes) for _ in range(len(base))]
     zs = [torch.empty((b.n_templates, blk), dtype=torch.complex64, device="cuda") for b in base]
     fs_step = sum(t.filter_samples_per_block(blk) for t in tables)
     flops = sum(W.algorithmic_flops(t, blk)["filter"] for t in tables)
     with torch.cuda.stream(stream):
         def step(i):
-            S.spiir_process_batch([(base[s], xt[s][i * blk:(i + 1) * blk], zs[s], wss[s])
-                                   for s in range(n_streams)], stream=stream)
+            reqs = [(base[b], xt[streams_of[b]][i * blk:(i + 1) * blk], zs[b], wss[b])
+                    for b in range(len(base))]
+            for j in range(0, len(reqs), S.MAX_BATCH):
+                S.spiir_process_batch(reqs[j:j + S.MAX_BATCH], stream=stream)
         for i in range(Wm):
             step(i)
         torch.cuda.synchronize()
@@ -240,6 +251,13 @@ def serving_bench(args, S, W, torch, np):
             evs[i + 1].record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prof = S.spiir_profile_read()
     S.spiir_profile_enable(False)
     for b in base:
@@ -254,7 +272,7 @@ def serving_bench(args, S, W, torch, np):
     launches_per_step = prof["filter"]["launches"] / K
     achieved = flops / launches_per_step / (filt_ms * 1e-3) / 1e12
     value = fs_step * K / wall
-    workload = f"cfg5-serving-{total_t}x7band-3streams"
+    workload = f"cfg5-serving-{total_t}x7band-3streams" + (f"-{len(base)}banks" if args.serve_split > 1 else "")
     print(f"serving: saturated step {wall / K * 1e3:.3f} ms, {value:.3e} fs/s", file=sys.stderr, flush=True)
 
     out = {
@@ -270,7 +288,8 @@ def serving_bench(args, S, W, torch, np):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "templates": total_t, "streams": n_streams, "bands": 7,
+        "config": {"workload": workload, "templates": total_t, "streams": n_streams, "banks": len(base),
+                   "bands": 7,
                    "base_rate_hz": rate, "filters": int(sum(t.total_filters for t in tables)),
                    "saturated_step": "one 1 s block (4096 samples) of every stream per batch",
                    "filters_per_lane": plan["filters_per_lane"],
@@ -295,7 +314,7 @@ def serving_bench(args, S, W, torch, np):
 
     # ---- 2. real-time capacity
     if args.serve_seconds > 0:
-        out["serving"] = serving_capacity(args, S, W, SV, torch, np, tables, base, ws_bytes,
+        out["serving"] = serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_bytes,
                                           fs_step, value, max_block, prec)
         cap = out["serving"]
         out["real_time_templates"] = cap["real_time_templates"]
@@ -304,17 +323,17 @@ def serving_bench(args, S, W, torch, np):
     for b in base:
         b.destroy()
     if args.cpu_budget > 0:
-        wl = W.Workload(f"{workload}-bank0", tables[0], rate, K + Wm, 2000)
+        wl = W.Workload(f"{workload}-bank0", tables[0], rate, max(K + Wm, 64), 2000)
         out["cpu_baseline"] = cpu_baseline(wl, rate, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 
-def serving_capacity(args, S, W, SV, torch, np, tables, base, ws_bytes, fs_step, sat_value,
+def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_bytes, fs_step, sat_value,
                      max_block, prec):
-    """Largest resident template count (in copies of the three banks) that the
+    """Largest resident template count (in copies of the stream banks) that the
     continuous-batching scheduler serves at real-time Poisson arrivals, and the
     plain form at the same count and at its own largest sustained count."""
-    n_streams = len(tables)
+    n_streams = 1 + max(streams_of)
     per_set = sum(t.n_templates for t in tables)
     rate = 4096
     bank_pool = {id(t): [b] for t, b in zip(tables, base)}
@@ -338,14 +357,14 @@ def serving_capacity(args, S, W, SV, torch, np, tables, base, ws_bytes, fs_step,
     # allocator rounds every array up: keep 10% back
     budget = int(0.9 * (free - 1.1 * pool_bytes)) + fp_set
     k_hbm = max(1, budget // fp_set)
-    # arrival work per copy of the three banks, per second of data
+    # arrival work per copy of the stream banks, per second of data
     fs_per_set_s = fs_step  # one 1 s block of every stream = one second of data
     k_est = sat_value / fs_per_set_s
     print(f"capacity: footprint {fp_set / per_set / 1024:.1f} KiB/template, HBM admits {k_hbm} copies "
           f"({k_hbm * per_set} templates), saturated rate sustains ~{k_est:.0f}", file=sys.stderr, flush=True)
 
     def trial(policy, k):
-        units = [(s, tables[s]) for _ in range(k) for s in range(n_streams)]
+        units = [(streams_of[b], tables[b]) for _ in range(k) for b in range(len(tables))]
         be = backend()
         sch = SV.Scheduler(be, units=units, max_block=max_block, hbm_budget=budget, policy=policy,
                            abort_backlog_s=args.serve_backlog_s)
@@ -381,8 +400,20 @@ def serving_capacity(args, S, W, SV, torch, np, tables, base, ws_bytes, fs_step,
 
     k_b, runs_b = search("batched", int(np.ceil(k_est * 1.02)))
     plain_same = trial("plain", k_b) if k_b > 0 else None
-    k_p, runs_p = (search("plain", k_b, first=plain_same) if plain_same and plain_same["sustained"]
-                   else search("plain", next_k(plain_same, k_b)) if k_b > 0 else (0, []))
+    if plain_same is not None and plain_same["sustained"]:
+        # plain keeps up where batched does: try it where batched fell behind
+        k_p, runs_p = k_b, [plain_same]
+        above = [r["copies"] for r in runs_b if not r["sustained"] and r["copies"] > k_b]
+        if above:
+            r = trial("plain", min(above))
+            runs_p.append(r)
+            if r["sustained"]:
+                k_p = r["copies"]
+    elif k_b > 0:
+        k_p, runs_p = search("plain", next_k(plain_same, k_b))
+        runs_p = [plain_same] + runs_p
+    else:
+        k_p, runs_p = 0, []
     best_b = next((r for r in runs_b if r["copies"] == k_b), None)
     best_p = next((r for r in runs_p if r["copies"] == k_p), None)
     keys = ("copies", "templates", "sustained", "aborted", "p50_ms", "p99_ms", "max_ms", "drain_s",
@@ -418,11 +449,13 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="config 5: seconds of data per stream in each real-time capacity run "
                          "(0 = saturated step only)")
-    ap.add_argument("--serve-backlog-s", type=float, default=3.0,
+    ap.add_argument("--serve-backlog-s", type=float, default=5.0,
                     help="config 5: a capacity run stops once its oldest unfinished block is this old")
-    ap.add_argument("--serve-drain-s", type=float, default=1.5,
+    ap.add_argument("--serve-drain-s", type=float, default=2.0,
                     help="config 5: a capacity run keeps up if it ends within this long after "
                          "the last arrival")
+    ap.add_argument("--serve-split", type=int, default=1,
+                    help="config 5: split each stream's templates into this many banks")
     ap.add_argument("--templates", type=int, default=None)
     ap.add_argument("--filters-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)

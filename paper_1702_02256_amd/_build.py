@@ -36,5 +36,26 @@ def build_library(force: bool = True, verbose: bool = False) -> str:
     return LIB
 
 
+C_ABI_SRC = os.path.join(ROOT, "tests", "c", "spiir_c_abi.c")
+C_ABI_BIN = os.path.join(ROOT, "tests", "c", "spiir_c_abi")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def build_c_abi(verbose: bool = False) -> str:
+    """The torch-free C consumer of the ABI (tests/c), linked against this
+    build of libspiir.so and ROCm's HIP runtime."""
+    tmp = C_ABI_BIN + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE,
+           "-I", os.path.join(ROCM, "include"), C_ABI_SRC, "-L", PKG, "-lspiir",
+           "-L", os.path.join(ROCM, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/../../paper_1702_02256_amd", "-Wl,-rpath," + os.path.join(ROCM, "lib"),
+           "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, C_ABI_BIN)
+    return C_ABI_BIN
+
+
 if __name__ == "__main__":
     print(build_library(verbose=True))

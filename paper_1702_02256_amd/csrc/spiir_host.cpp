@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -894,6 +895,12 @@ hipError_t wait_banks(int32_t n_req, const spiir_request* req, hipStream_t s)
     return e;
 }
 
+// Test hook for the failure path: with SPIIR_TEST_FAIL_ENQUEUE set in the
+// environment when the library loads, every launch sequence fails before its
+// first launch (as a rejected launch would), so tests can reach the poisoned-
+// bank path without a device fault.
+const bool g_fail_enqueue = std::getenv("SPIIR_TEST_FAIL_ENQUEUE") != nullptr;
+
 // Kernels of one batch on `s`: per inner chunk of at most kInnerBlock base-rate
 // samples, the staging kernel (which advances each bank's device clock), the
 // filter kernel and the upsample-and-add kernel.  Reads no host-side sample
@@ -901,7 +908,7 @@ hipError_t wait_banks(int32_t n_req, const spiir_request* req, hipStream_t s)
 hipError_t enqueue_batch(int32_t n_req, const spiir_request* req, hipStream_t s, bool prof,
                          spiir_peak* const* peaks = nullptr, float thr2 = 0.0f)
 {
-    hipError_t e = hipSuccess;
+    hipError_t e = g_fail_enqueue ? hipErrorLaunchFailure : hipSuccess;
     int64_t maxn = 0;
     for (int r = 0; r < n_req; ++r) maxn = std::max<int64_t>(maxn, req[r].n);
     for (int64_t c0 = 0; c0 < maxn && e == hipSuccess; c0 += kInnerBlock) {

@@ -119,6 +119,10 @@ def load_library():
             "`python -c 'import __graft_entry__ as g; g.build()'` (there is no fallback path)")
     _torch_hip_first()
     lib = C.CDLL(LIB_PATH)
+    paths = hip_runtime_paths()
+    if len(paths) > 1:
+        raise ImportError("two HIP runtimes are mapped in this process (%s): the library and the "
+                          "GPU memory it is given must use one" % ", ".join(paths))
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     sig = {
         "spiir_footprint": (C.c_int, [C.POINTER(BankDesc), C.POINTER(C.c_size_t)]),
@@ -151,6 +155,26 @@ def load_library():
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def hip_runtime_paths() -> list:
+    """Distinct files of the HIP runtime (libamdhip64) mapped in this process.
+
+    The library links libamdhip64.so.7 by that soname.  When torch is imported
+    first, its bundled runtime, which carries the same soname, is already
+    mapped and the loader binds the library to it, so the library, torch's
+    allocator and torch's streams share one runtime; a process without torch
+    maps ROCm's.  Two distinct files here would mean two runtimes."""
+    out = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                i = line.find("/")
+                if i >= 0 and os.path.basename(line[i:].strip()).startswith("libamdhip64"):
+                    out.add(os.path.realpath(line[i:].strip()))
+    except OSError:
+        pass
+    return sorted(out)
 
 
 def header_symbols() -> list:

@@ -55,7 +55,36 @@ def test_serving_equals_alone(policy, speed):
     for s in range(3):
         got = _collect(be, s)
         assert np.array_equal(got, _alone(banks[s], xs[s])), s
-    zr = oracle.run_stream(banks[0].subset([0, 1]), xs[0])
-    got = _collect(be, 0)[:2].astype(np.complex128)
-    err = np.max(np.abs(got - zr), axis=1) / np.max(np.abs(zr), axis=1)
-    assert err.max() <= 1e-5
+    for s in range(3):  # sampled templates of every stream against the oracle
+        sel = [0, 17 + s, 47]
+        zr = oracle.run_stream(banks[s].subset(sel), xs[s])
+        got = _collect(be, s)[sel].astype(np.complex128)
+        err = np.max(np.abs(got - zr), axis=1) / np.max(np.abs(zr), axis=1)
+        assert err.max() <= 1e-5, (s, err)
+
+
+def test_admission_by_footprint_on_the_device():
+    """The HBM budget holds two of the three banks: the third waits until a
+    stream ends and its bank is released, then starts from its stream's first
+    block; every stream's output still equals the stream alone and the oracle."""
+    from paper_1702_02256_amd import spiir as S
+    banks = _banks(T=32, seed=12)
+    arr = W.serving_arrivals(78, 3, 3.0, rate_hz=4096, speed=20.0)
+    arr = [(l[: 2 + 3 * s], t[: 2 + 3 * s]) for s, (l, t) in enumerate(arr)]  # streams end one after another
+    xs = [W.noise_stream(400 + s, int(l.sum())) for s, (l, _) in enumerate(arr)]
+    fp = [S.spiir_footprint(b, 8192) for b in banks]
+    budget = fp[0] + fp[1] + 1
+    assert fp[2] > budget - fp[0] - fp[1]
+    be = SV.HipBackend(xs, n_streams=2, keep_outputs=True)
+    sch = SV.Scheduler(be, banks, max_block=8192, hbm_budget=budget)
+    st = sch.run(SV.make_arrivals(arr), release_finished=True)
+    print(st.summary(), st.admitted_at, flush=True)
+    assert st.admitted_at[0] == 0.0 and st.admitted_at[1] == 0.0
+    assert st.admitted_at[2] > 0.0, "the third bank must wait for the budget"
+    assert sch.used <= budget
+    for s in range(3):
+        got = _collect(be, s)
+        assert np.array_equal(got, _alone(banks[s], xs[s])), s
+        zr = oracle.run_stream(banks[s].subset([1, 30]), xs[s])
+        err = np.max(np.abs(got[[1, 30]].astype(np.complex128) - zr), axis=1) / np.max(np.abs(zr), axis=1)
+        assert err.max() <= 1e-5, (s, err)
