@@ -367,7 +367,8 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
         units = [(streams_of[b], tables[b]) for _ in range(k) for b in range(len(tables))]
         be = backend()
         sch = SV.Scheduler(be, units=units, max_block=max_block, hbm_budget=budget, policy=policy,
-                           abort_backlog_s=args.serve_backlog_s)
+                           abort_backlog_s=args.serve_backlog_s, max_inflight=args.serve_inflight,
+                           merge_max=args.serve_merge_max)
         st = sch.run(SV.make_arrivals(arr))
         sch.release_all()
         torch.cuda.synchronize()
@@ -385,7 +386,7 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
         """After a run that fell behind: the count its served rate would carry
         (98%), and at least 3% fewer copies."""
         served = r["filter_samples_per_s"] / fs_per_set_s
-        return max(1, min(k - 1, int(k * 0.97), int(0.98 * served)))
+        return max(1, min(k - 1, int(k * 0.97), max(int(0.98 * served), int(0.6 * k))))
 
     def search(policy, k_hi, first=None):
         """Descend from k_hi until a run keeps up (`first`: a run at k_hi already made)."""
@@ -454,6 +455,10 @@ def main():
     ap.add_argument("--serve-drain-s", type=float, default=2.0,
                     help="config 5: a capacity run keeps up if it ends within this long after "
                          "the last arrival")
+    ap.add_argument("--serve-inflight", type=int, default=2,
+                    help="config 5: batches the batched policy keeps on the device at once")
+    ap.add_argument("--serve-merge-max", type=int, default=8192,
+                    help="config 5: longest request (samples) the batched policy forms by merging blocks")
     ap.add_argument("--serve-split", type=int, default=1,
                     help="config 5: split each stream's templates into this many banks")
     ap.add_argument("--templates", type=int, default=None)

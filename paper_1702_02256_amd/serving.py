@@ -101,12 +101,14 @@ class Scheduler:
     ``units``: a list of (stream, tables), several banks per stream allowed.
     ``abort_backlog_s``: stop once the oldest block not yet filtered by every
     bank of its stream is older than this (the device is not keeping up); the
-    work in flight is drained first.
+    work in flight is drained first.  ``merge_max``: the longest request that
+    merging consecutive blocks may form (default ``max_block``).
     """
 
     def __init__(self, backend, tables_per_stream=None, max_block: int = 4096,
                  hbm_budget: int | None = None, policy: str = "batched", max_batch: int = 16,
-                 max_inflight: int = 2, units=None, abort_backlog_s: float | None = None):
+                 max_inflight: int = 2, units=None, abort_backlog_s: float | None = None,
+                 merge_max: int | None = None):
         if policy not in ("batched", "plain"):
             raise ValueError(policy)
         if units is None:
@@ -117,6 +119,7 @@ class Scheduler:
         self.stream_units = [[u for u, (s, _) in enumerate(self.units) if s == st]
                              for st in range(self.n_streams)]
         self.max_block = int(max_block)
+        self.merge_max = min(int(merge_max), self.max_block) if merge_max else self.max_block
         self.policy = policy
         self.max_batch = 1 if policy == "plain" else int(max_batch)
         self.max_inflight = 1 if policy == "plain" else int(max_inflight)
@@ -175,7 +178,7 @@ class Scheduler:
             take, n = [first], first.n
             i = self.cursor[u] + 1
             if self.policy == "batched":
-                while i < len(blocks) and n + blocks[i].n <= self.max_block:
+                while i < len(blocks) and n + blocks[i].n <= self.merge_max:
                     take.append(blocks[i])
                     n += blocks[i].n
                     i += 1
@@ -184,12 +187,13 @@ class Scheduler:
         return reqs
 
     def _retire_ready(self, t0: float, block_until_done: bool = False):
-        """Stamp and drop the leading in-flight batches that have completed."""
+        """Stamp and drop the leading in-flight batches that have completed,
+        then drop the finished blocks at the head of each stream's backlog."""
         while self.inflight:
             ticket, reqs = self.inflight[0]
             if not self.be.done(ticket):
                 if not block_until_done:
-                    return
+                    break
                 self.be.wait(ticket, None)
                 continue
             t = self.be.clock() - t0

@@ -184,3 +184,38 @@ def test_backlog_bound_stops_an_overloaded_run():
     assert summ["blocks"] < summ["blocks_arrived"]
     # the run stopped about when the oldest unfinished block became 1 s old
     assert st.wall < 6.0
+
+
+class _CostBackend(VirtualOracleBackend):
+    """Timing only: a serial device at a fixed filter-sample rate (no filtering)."""
+
+    def create(self, tables, max_block):
+        return object()
+
+    def destroy(self, b):
+        pass
+
+    def submit(self, items):
+        cost = self.launch_s + sum(self.s_per_fs * tb for tb in (self._fs(n) for _, _, _, n in items))
+        begin = max(self.t, self.busy_until)
+        self.busy_until = begin + cost
+        return {"done_at": self.busy_until}
+
+    def _fs(self, n):
+        return 1e6 * n
+
+
+def test_backlog_counts_only_unfinished_blocks_with_two_batches_in_flight():
+    """With a second batch always on the device, finished blocks must still
+    leave the backlog: a run with spare throughput is not stopped."""
+    banks, arr, xs = _setup(n_streams=3, dur_s=8.0, speed=1.0)
+    units = [(s, banks[s]) for _ in range(60) for s in range(3)]
+    # 60 banks per stream; the device runs at about 1.15x the arrival rate,
+    # so a batch is nearly always on it
+    be = _CostBackend(xs, s_per_fs=1.0 / (1.15 * 60 * 3 * 1e6 * 256), launch_s=1e-5)
+    sch = SV.Scheduler(be, units=units, max_block=1024, policy="batched", max_batch=8,
+                       abort_backlog_s=2.0)
+    st = sch.run(SV.make_arrivals(arr))
+    summ = st.summary()
+    assert not st.aborted, summ
+    assert summ["blocks"] == summ["blocks_arrived"]
