@@ -323,7 +323,7 @@ def serving_bench(args, S, W, torch, np):
     for b in base:
         b.destroy()
     if args.cpu_budget > 0:
-        wl = W.Workload(f"{workload}-bank0", tables[0], rate, max(K + Wm, 64), 2000)
+        wl = W.Workload(f"{workload}-bank0", tables[0], rate, max(K + Wm, 160), 2000)
         out["cpu_baseline"] = cpu_baseline(wl, rate, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
@@ -340,6 +340,10 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
     be_kw = dict(precision=prec, workspace=S.WORKSPACE_CALLER)
     dur = args.serve_seconds
     arr = W.serving_arrivals(5005, n_streams, dur, rate_hz=rate, speed=1.0)
+    # Poisson arrival times scaled per stream so that its last block arrives
+    # when its data ends: over the run every stream delivers exactly one second
+    # of data per second (an unscaled draw can run ahead of or behind real time)
+    arr = [(l, t * (l.sum() / rate) / t[-1]) for l, t in arr]
     xs = [W.noise_stream(2100 + s, int(l.sum())) for s, (l, _) in enumerate(arr)]
 
     def backend():
@@ -388,33 +392,34 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
         served = r["filter_samples_per_s"] / fs_per_set_s
         return max(1, min(k - 1, int(k * 0.97), max(int(0.98 * served), int(0.6 * k))))
 
-    def search(policy, k_hi, first=None):
-        """Descend from k_hi until a run keeps up (`first`: a run at k_hi already made)."""
-        runs, k = [], max(1, min(k_hi, k_hbm))
-        while True:
+    def search(policy, k0, first=None, max_runs=5):
+        """From k0: up in 4% steps while runs keep up, else down until one does
+        (`first`: a run at k0 already made).  Returns the largest count that
+        kept up (0 if none) and the runs."""
+        runs, k = [], max(1, min(k0, k_hbm))
+        best, worst_fail = 0, None
+        while len(runs) < max_runs:
             r = first if first is not None and first["copies"] == k else trial(policy, k)
             first = None
             runs.append(r)
-            if r["sustained"] or k == 1:
-                return (k if r["sustained"] else 0), runs
-            k = next_k(r, k)
-
-    k_b, runs_b = search("batched", int(np.ceil(k_est * 1.02)))
-    plain_same = trial("plain", k_b) if k_b > 0 else None
-    if plain_same is not None and plain_same["sustained"]:
-        # plain keeps up where batched does: try it where batched fell behind
-        k_p, runs_p = k_b, [plain_same]
-        above = [r["copies"] for r in runs_b if not r["sustained"] and r["copies"] > k_b]
-        if above:
-            r = trial("plain", min(above))
-            runs_p.append(r)
             if r["sustained"]:
-                k_p = r["copies"]
-    elif k_b > 0:
-        k_p, runs_p = search("plain", next_k(plain_same, k_b))
-        runs_p = [plain_same] + runs_p
-    else:
-        k_p, runs_p = 0, []
+                best = max(best, k)
+                nk = min(k_hbm, max(k + 1, int(k * 1.04)))
+                if nk == k or (worst_fail is not None and nk >= worst_fail):
+                    break
+            else:
+                worst_fail = k if worst_fail is None else min(worst_fail, k)
+                if best:
+                    break
+                nk = next_k(r, k)
+                if nk == k:
+                    break
+            k = nk
+        return best, runs
+
+    k_b, runs_b = search("batched", int(round(k_est)))
+    plain_same = trial("plain", k_b) if k_b > 0 else None
+    k_p, runs_p = search("plain", k_b, first=plain_same) if plain_same is not None else (0, [])
     best_b = next((r for r in runs_b if r["copies"] == k_b), None)
     best_p = next((r for r in runs_p if r["copies"] == k_p), None)
     keys = ("copies", "templates", "sustained", "aborted", "p50_ms", "p99_ms", "max_ms", "drain_s",
@@ -452,7 +457,7 @@ def main():
                          "(0 = saturated step only)")
     ap.add_argument("--serve-backlog-s", type=float, default=5.0,
                     help="config 5: a capacity run stops once its oldest unfinished block is this old")
-    ap.add_argument("--serve-drain-s", type=float, default=2.0,
+    ap.add_argument("--serve-drain-s", type=float, default=0.5,
                     help="config 5: a capacity run keeps up if it ends within this long after "
                          "the last arrival")
     ap.add_argument("--serve-inflight", type=int, default=2,
