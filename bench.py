@@ -219,7 +219,8 @@ def serving_bench(args, S, W, torch, np):
     max_block = 8192
     prec = args.precision
     stream = torch.cuda.Stream()
-    base = [S.Bank(t, max_block, stream=stream, precision=prec, workspace=S.WORKSPACE_CALLER)
+    shape = dict(filters_per_lane=args.filters_per_lane, waves_per_group=args.waves_per_group)
+    base = [S.Bank(t, max_block, stream=stream, precision=prec, workspace=S.WORKSPACE_CALLER, **shape)
             for t in tables]
     print(f"serving: {total_t} templates in {len(base)} banks created", file=sys.stderr, flush=True)
     ws_bytes = max(b.workspace_bytes for b in base)
@@ -337,7 +338,8 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
     per_set = sum(t.n_templates for t in tables)
     rate = 4096
     bank_pool = {id(t): [b] for t, b in zip(tables, base)}
-    be_kw = dict(precision=prec, workspace=S.WORKSPACE_CALLER)
+    be_kw = dict(precision=prec, workspace=S.WORKSPACE_CALLER, filters_per_lane=args.filters_per_lane,
+                 waves_per_group=args.waves_per_group)
     dur = args.serve_seconds
     arr = W.serving_arrivals(5005, n_streams, dur, rate_hz=rate, speed=1.0)
     # Poisson arrival times scaled per stream so that its last block arrives

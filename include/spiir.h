@@ -61,7 +61,7 @@ enum {
 /* Arithmetic of the filter sum. */
 enum {
     SPIIR_FP32 = 0,             /* complex FP32, plain summation over filters      */
-    SPIIR_FP32_COMPENSATED = 1  /* complex FP32, error-free (TwoSum) cross-lane sum */
+    SPIIR_FP32_COMPENSATED = 1  /* complex FP32 filters, cross-lane sums in FP64   */
 };
 
 /*
@@ -89,11 +89,10 @@ enum {
  *                         create; a power of two in [16, 1024]; 0 = 32.
  *   filters_per_lane      F in {1, 2, 4, 6, 8}; 0 = library default.  With
  *                         both this and waves_per_group 0 the library takes
- *                         F = 4 with 8 waves (plain sum) or F = 6 with 4
- *                         waves (compensated sum) for banks that fill the
- *                         device with such workgroups (multi-rate banks:
- *                         with at least 4 or 3 rounds of them), and F = 4
- *                         with 4 waves otherwise.
+ *                         F = 4 with 8 waves for banks that fill the device
+ *                         with such workgroups (multi-rate banks: with at
+ *                         least 4 rounds of them), and F = 4 with 4 waves
+ *                         otherwise.
  *   waves_per_group       wave64s per workgroup in [1, 16] ([1, 8] when
  *                         filters_per_lane is 8); 0 = default (as above;
  *                         with F given: 8, or 4 with 6 or more filters per

@@ -19,7 +19,7 @@ import json
 import os
 import time
 
-DEFAULT_CANDIDATES = [(2, 4), (2, 8), (4, 4), (4, 8), (6, 4), (8, 4)]
+DEFAULT_CANDIDATES = [(2, 4), (2, 8), (4, 4), (4, 8), (6, 4), (6, 8), (8, 4)]
 # banks with fewer lanes than this cannot fill the device with filters alone;
 # for them the tuner also tries splitting each block in time
 SMALL_BANK_LANES = 65536

@@ -19,12 +19,12 @@ using namespace spiir;
 namespace {
 
 // Default launch shape of a bank that fills the device (make_plan_fixed
-// takes 4 filters per lane in 4-wave groups for the others).  The plain sum:
-// 4 filters per lane, 8 waves per group.  The compensated sum spends more per
-// cross-lane addition, so it gains from covering more filters per lane: 6
-// filters per lane, and with them 4 waves per group (128 VGPRs).
+// takes 4 filters per lane in 4-wave groups for the others): 4 filters per
+// lane, 8 waves per group, with either sum.  The compensated sum's FP64
+// cross-lane additions cost about what the plain ones do, so it gains nothing
+// from covering more filters per lane (config 3, ms per block: F = 4, W = 8
+// 1.122; F = 6, W = 4 1.168; F = 6, W = 8 1.194; F = 8, W = 4 1.333).
 constexpr int kDefaultF = 4;
-constexpr int kDefaultFComp = 6;
 constexpr int kDefaultW = 8;
 constexpr int kDefaultWWide = 4;  // with 6 or 8 filters per lane
 constexpr int kDefaultC = 32;
@@ -39,8 +39,7 @@ constexpr int64_t kStateHeaderBytes = 128;
 
 int default_filters_per_lane(const spiir_bank_desc* d)
 {
-    if (d->filters_per_lane) return d->filters_per_lane;
-    return d->precision == SPIIR_FP32_COMPENSATED ? kDefaultFComp : kDefaultF;
+    return d->filters_per_lane ? d->filters_per_lane : kDefaultF;
 }
 
 int default_waves_per_group(int F) { return F >= 6 ? kDefaultWWide : kDefaultW; }
@@ -381,6 +380,11 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub, int copie
     for (size_t i = 0; i < p.lane_meta.size(); ++i)
         if ((p.lane_meta[i] & 0xffff) != kSlotNone && (i & 1) == 0) return SPIIR_EINVAL;
 
+    // The run-sum rows of the filter kernel's level 2 are nrun_max entries
+    // apart; an odd stride keeps the 16 sample rows a level-1 store or a
+    // level-2 read touches at once on distinct LDS bank pairs (an even stride
+    // such as 24 made each such 64-bit store take 30 LDS cycles instead of 4).
+    p.nrun_max |= 1;
     p.lds_filter = p.copies * p.xcap * 4 + (L / 2) * (kTile + 1) * 8 + 2 * kTile * p.nrun_max * 8 + p.npiece_max * 8 +
                    L * 4 + p.npiece_max * 8;
     p.lds_stage = ((p.td - 1) + p.mb_inner + (p.td - 1) + p.mb_inner / 2 + p.td) * 4;
@@ -494,19 +498,18 @@ double group_rounds(const Plan& p)
 }
 
 // The default launch shape (no filters_per_lane and no waves_per_group given).
-// The shapes that run a full bank fastest (F = 6, W = 4 compensated; F = 4,
-// W = 8 plain) have large workgroups.  A bank that does not fill the device
-// with them, or a multi-rate bank with only a few rounds of them (its band-0
-// workgroups, the longest, then decide when the block ends), runs faster in
-// workgroups of 4 waves with 4 filters per lane: more, smaller workgroups
-// balance better.  Measured, ms per block (large shape -> F = 4, W = 4):
-// compensated, config-3 banks of 1024, 2048, 3072, 4096 templates (1.1, 2.1,
-// 3.2, 4.3 rounds) 0.80 -> 0.66, 0.98 -> 0.86, 1.03 -> 1.10, 1.34 -> 1.45;
-// the uneven bank of 8192 templates (1.9 rounds) 1.42 -> 1.31; the single-rate
-// bank of 1024 x 512 filters (0.7 rounds) 0.47 -> 0.38.  Plain: config-3 banks
-// of 1024, 2048, 3072, 4096 templates (1.2, 2.4, 3.6, 4.8 rounds) 0.71 -> 0.61,
-// 0.93 -> 0.79, 1.19 -> 1.05, 1.32 -> 1.38; the uneven bank (2.0 rounds) 1.31
-// -> 1.21; the single-rate bank (1.0 round) 0.348 -> 0.355.
+// The shape that runs a full bank fastest (F = 4, W = 8) has large
+// workgroups.  A bank that does not fill the device with them, or a
+// multi-rate bank with fewer than 4 rounds of them (its band-0 workgroups, the
+// longest, then decide when the block ends), runs faster in workgroups of 4
+// waves: more, smaller workgroups balance better.  Measured, ms per block
+// (F = 4, W = 8 -> F = 4, W = 4), compensated: config-3 banks of 1024, 2048,
+// 3072, 4096 templates (1.2, 2.4, 3.6, 4.8 rounds) 0.68 -> 0.58, 0.86 -> 0.76,
+// 1.10 -> 1.00, 1.25 -> 1.32; the uneven bank of 8192 templates (2.0 rounds)
+// 1.33 -> 1.23; the single-rate bank of 1024 x 512 filters (1.0 round) 0.333 ->
+// 0.346.  Plain, before the compensated sum moved to FP64: config-3 banks
+// 0.71 -> 0.61, 0.93 -> 0.79, 1.19 -> 1.05, 1.32 -> 1.38; the uneven bank 1.31
+// -> 1.21; the single-rate bank 0.348 -> 0.355.
 int make_plan_fixed(const spiir_bank_desc* d, Plan& p)
 {
     if (!d) return SPIIR_EINVAL;
@@ -516,7 +519,7 @@ int make_plan_fixed(const spiir_bank_desc* d, Plan& p)
     int bands_used = 0;
     for (int h = 0; h < p.H; ++h) bands_used += p.band_wg0[h + 1] > p.band_wg0[h];
     const double rounds = group_rounds(p);
-    const double keep = bands_used > 1 ? (p.precision == SPIIR_FP32_COMPENSATED ? 3.0 : 4.0) : 1.0;
+    const double keep = bands_used > 1 ? 4.0 : 1.0;
     if (rounds >= keep || (p.F == 4 && p.W <= 4)) return SPIIR_OK;
     spiir_bank_desc d4 = *d;
     d4.filters_per_lane = 4;

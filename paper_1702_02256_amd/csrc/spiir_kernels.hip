@@ -14,17 +14,14 @@
 
 #include <climits>
 #include <mutex>
+#include <type_traits>
 
 #include "spiir_internal.h"
 
 namespace spiir {
 
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
-{
-    s = a + b;
-    const float bp = s - a;
-    e = (a - (s - bp)) + (b - bp);
-}
+__device__ __forceinline__ float acc_fma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double acc_fma(double a, double b, double c) { return fma(a, b, c); }
 
 // Address-space views of device memory.  Pointers held in the bank
 // descriptor are generic; through a generic pointer the compiler emits flat
@@ -191,15 +188,25 @@ __device__ __forceinline__ void one_step(const float (&xv)[F], float* __restrict
 // A full tile of kTile samples starting at an absolute multiple of kTile.
 // x2[f] points at the 8-byte aligned pair (x[k - d], x[k + 1 - d]) of filter f
 // in the window copy of its delay's parity, so one ds_read_b64 feeds two
-// samples.  The restrict qualifiers tell the compiler that the partial-sum
-// stores never alias the window, so later loads can be issued ahead of them.
+// samples.  Each pair stays one ds_read_b64: the pair is a native vector (a
+// struct would be split into two 32-bit loads), and the scheduling barrier
+// after each step's loads keeps the compiler from fusing the reads of
+// consecutive pairs into ds_read2_b64.  On gfx950 a wave's ds_read_b64 whose
+// 32-lane halves touch distinct bank pairs takes 2 LDS cycles, while a
+// ds_read2_b64 over the same addresses took 15 (measured with
+// SQ_LDS_IDX_ACTIVE and SQ_LDS_BANK_CONFLICT), so the fused form made the
+// window reads the largest LDS cost and undid the bank-aware placement.  The
+// barrier still lets the next step's loads be issued during this step's
+// arithmetic.  The restrict qualifiers tell the compiler that the
+// partial-sum stores never alias the window.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 template <int F, bool SUM>
-__device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* __restrict__ pcol,
+__device__ __forceinline__ void tile_full(const f32x2_t* const (&xp)[F], float* __restrict__ pcol,
                                           const float (&ar)[F],
                                           const float (&ai)[F], const float (&br)[F],
                                           const float (&bi)[F], float (&yr)[F], float (&yi)[F])
 {
-    const float2* __restrict__ x2[F];
+    const f32x2_t* __restrict__ x2[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) x2[f] = xp[f];
 #pragma unroll
@@ -207,10 +214,11 @@ __device__ __forceinline__ void tile_full(const float2* const (&xp)[F], float* _
         float xa[F], xb[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            const float2 v = x2[f][jj];
+            const f32x2_t v = x2[f][jj];
             xa[f] = v.x;
             xb[f] = v.y;
         }
+        __builtin_amdgcn_sched_barrier(0);
         one_step<F, SUM>(xa, pcol, 2 * jj, ar, ai, br, bi, yr, yi);
         one_step<F, SUM>(xb, pcol, 2 * jj + 1, ar, ai, br, bi, yr, yi);
     }
@@ -292,6 +300,9 @@ constexpr int kStageBatch = 4;  // window loads a thread keeps in flight
 template <int F, bool COMP, bool LOCAL>
 __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COMP)) k_filter(LaunchArgs args)
 {
+    // Accumulator of the cross-lane sums: FP32 for the plain sum, FP64 for the
+    // compensated one.
+    using Acc = typename std::conditional<COMP, double, float>::type;
     extern __shared__ float sm[];
     const int bid = blockIdx.x;
     int lo = 0, hi = args.nseg;
@@ -377,9 +388,13 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
     }
     __syncthreads();
 
-    // level-1 role: sample row j1 of the 16-lane group q1; runs end where endmask is set
+    // level-1 role: sample row j1 of the 16-lane group q1; runs end where endmask
+    // is set.  A wave reduces its own four groups; the first half-wave takes
+    // groups 0 and 2 of them and the second 1 and 3, so that the two groups one
+    // 32-lane half reads are 16 pair entries apart, 32 banks apart in the
+    // [L/2][kTile+1] tile, and its 64-bit reads never share a bank pair.
     const int j1 = tid & (kTile - 1);
-    const int q1 = tid / kTile;
+    const int q1 = (tid >> 6) * 4 + (((tid >> 4) & 1) << 1) + ((tid >> 5) & 1);
     unsigned endmask = 0;
     int slot0 = -1;
 #pragma unroll
@@ -437,11 +452,11 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
             if (cnt > kb + sub - k) cnt = kb + sub - k;
             const int rel = (int)(kabs - origin);  // window position of sample k
             if (cnt == kTile && two_copies) {
-                const float2* xp[F];
+                const f32x2_t* xp[F];
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     const int par = dl[f] & 1;
-                    xp[f] = reinterpret_cast<const float2*>((par ? E1 : E0) + (rel - dl[f] - par));
+                    xp[f] = reinterpret_cast<const f32x2_t*>((par ? E1 : E0) + (rel - dl[f] - par));
                 }
                 tile_full<F, !LOCAL>(xp, pcol, ar, ai, br, bi, yr, yi);
             } else if (cnt == kTile) {
@@ -477,19 +492,24 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 c32* l2 = l2buf + parity * (kTile * nrun);
                 // level 1: each thread sums one sample row over the runs of a 16-lane group
-                // (all 16 partials are loaded before any run result is stored)
+                // (all 16 partials are loaded before any run result is stored); each run
+                // sum is rounded to FP32 once
                 if (j1 < cnt) {
                     constexpr int kPairs = kRunLanes / 2;
                     const int e0 = q1 * kPairs;
                     const c32* grp = pbuf + e0 * (kTile + 1) + j1;
+                    // one ds_read_b64 each (the barriers keep the compiler from
+                    // pairing them into ds_read2_b64, which takes twice as long)
                     c32 v[kPairs];
     #pragma unroll
-                    for (int i = 0; i < kPairs; ++i) v[i] = grp[i * (kTile + 1)];
+                    for (int i = 0; i < kPairs; ++i) {
+                        v[i] = grp[i * (kTile + 1)];
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                     c32* out = l2 + j1 * nrun;
                     if (wave_single_run) {
-                        // the whole group is one run: a pairwise tree (short dependency
-                        // chains), error-free additions when compensated
-                        float tr[kPairs], ti[kPairs], er = 0.0f, ei = 0.0f;
+                        // the whole group is one run: a pairwise tree (short dependency chains)
+                        Acc tr[kPairs], ti[kPairs];
     #pragma unroll
                         for (int i = 0; i < kPairs; ++i) {
                             tr[i] = v[i].x;
@@ -499,40 +519,24 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
                         for (int st = 1; st < kPairs; st *= 2)
     #pragma unroll
                             for (int i = 0; i + st < kPairs; i += 2 * st) {
-                                if (COMP) {
-                                    float e1, e2;
-                                    two_sum(tr[i], tr[i + st], tr[i], e1);
-                                    two_sum(ti[i], ti[i + st], ti[i], e2);
-                                    er += e1;
-                                    ei += e2;
-                                } else {
-                                    tr[i] += tr[i + st];
-                                    ti[i] += ti[i + st];
-                                }
+                                tr[i] += tr[i + st];
+                                ti[i] += ti[i + st];
                             }
-                        out[slot0] = (COMP ? c32{tr[0] + er, ti[0] + ei} : c32{tr[0], ti[0]});
+                        out[slot0] = c32{(float)tr[0], (float)ti[0]};
                     } else {
                         // runs in order; the accumulator restarts after a run end by a
                         // multiplication with keep = 0 (exact, and no selects)
                         int slot = slot0;
-                        float accr = v[0].x, acci = v[0].y, er = 0.0f, ei = 0.0f;
+                        Acc accr = v[0].x, acci = v[0].y;
     #pragma unroll
                         for (int i = 0; i < kPairs; ++i) {
                             if (i > 0) {
-                                const float keep = (float)(((endmask >> (i - 1)) & 1u) ^ 1u);
-                                if (COMP) {
-                                    float e1, e2;
-                                    two_sum(accr * keep, v[i].x, accr, e1);
-                                    two_sum(acci * keep, v[i].y, acci, e2);
-                                    er = fmaf(er, keep, e1);
-                                    ei = fmaf(ei, keep, e2);
-                                } else {
-                                    accr = fmaf(accr, keep, v[i].x);
-                                    acci = fmaf(acci, keep, v[i].y);
-                                }
+                                const Acc keep = (Acc)(((endmask >> (i - 1)) & 1u) ^ 1u);
+                                accr = acc_fma(accr, keep, (Acc)v[i].x);
+                                acci = acc_fma(acci, keep, (Acc)v[i].y);
                             }
                             if ((endmask >> i) & 1u) {
-                                out[slot] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
+                                out[slot] = c32{(float)accr, (float)acci};
                                 ++slot;
                             }
                         }
@@ -546,21 +550,13 @@ __global__ void __launch_bounds__(filter_max_threads(F), filter_min_waves(F, COM
                     if (j < cnt) {
                         const int2 rr = prun[p];
                         const c32* row = l2 + j * nrun;
-                        float accr = 0.0f, acci = 0.0f, er = 0.0f, ei = 0.0f;
+                        Acc accr = 0, acci = 0;
                         for (int s = rr.x; s < rr.y; ++s) {
                             const c32 v = row[s];
-                            if (COMP) {
-                                float e1, e2;
-                                two_sum(accr, v.x, accr, e1);
-                                two_sum(acci, v.y, acci, e2);
-                                er += e1;
-                                ei += e2;
-                            } else {
-                                accr += v.x;
-                                acci += v.y;
-                            }
+                            accr += v.x;
+                            acci += v.y;
                         }
-                        zwg[pzoff[p] + k + j] = (COMP ? c32{accr + er, acci + ei} : c32{accr, acci});
+                        zwg[pzoff[p] + k + j] = c32{(float)accr, (float)acci};
                     }
                 }
             }

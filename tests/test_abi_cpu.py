@@ -186,26 +186,28 @@ def test_automatic_time_split_follows_the_bank_size():
     assert S.spiir_plan(empty, 1024, time_chunks=auto)["time_chunks"] == 1
 
 
-def test_default_shape_follows_the_precision_and_the_bank_size():
-    # a full multi-rate bank: the large workgroups (6 filters per lane with the
-    # compensated sum, 8 waves with the plain one)
+def test_default_shape_follows_the_bank_size():
+    # a full multi-rate bank: the large workgroups (4 filters per lane, 8
+    # waves) with either sum
     big = W.config3(n_blocks=1).bank
-    plain = S.spiir_plan(big, 4096)
-    comp = S.spiir_plan(big, 4096, precision="fp32_compensated")
-    assert (plain["filters_per_lane"], plain["lanes_per_group"]) == (4, 512)
-    assert (comp["filters_per_lane"], comp["lanes_per_group"]) == (6, 256)
+    for prec in ("fp32", "fp32_compensated"):
+        p = S.spiir_plan(big, 4096, precision=prec)
+        assert (p["filters_per_lane"], p["lanes_per_group"]) == (4, 512), prec
     # every filter slot is a filter or padding: F = 6 packs segments in lanes of 6
-    assert comp["filter_slots"] % 6 == 0 and comp["filter_slots"] >= comp["total_filters"]
-    # a multi-rate bank with few rounds of them takes 4 filters per lane in
-    # 4-wave groups; a single-rate bank only when it does not fill the device
+    six = S.spiir_plan(big, 4096, precision="fp32_compensated", filters_per_lane=6)
+    assert six["lanes_per_group"] == 256
+    assert six["filter_slots"] % 6 == 0 and six["filter_slots"] >= six["total_filters"]
+    # a multi-rate bank with few rounds of them takes 4-wave groups; a
+    # single-rate bank only when it does not fill the device
     small = W.config3(n_templates=1024, n_blocks=1).bank
+    single = W.config2(n_blocks=1).bank
     for prec in ("fp32", "fp32_compensated"):
         p = S.spiir_plan(small, 4096, precision=prec)
         assert (p["filters_per_lane"], p["lanes_per_group"]) == (4, 256), prec
-    single = W.config2(n_blocks=1).bank
-    assert S.spiir_plan(single, 2048)["lanes_per_group"] == 512
-    p = S.spiir_plan(single, 2048, precision="fp32_compensated")
-    assert (p["filters_per_lane"], p["lanes_per_group"]) == (4, 256)
+        p = S.spiir_plan(single, 2048, precision=prec)
+        assert (p["filters_per_lane"], p["lanes_per_group"]) == (4, 512), prec
+        p = S.spiir_plan(W.config2(n_templates=256, n_blocks=1).bank, 2048, precision=prec)
+        assert (p["filters_per_lane"], p["lanes_per_group"]) == (4, 256), prec
     # an explicit F keeps its own default width; explicit shapes are kept
     bank = W.config3(n_templates=8, n_blocks=1).bank
     assert S.spiir_plan(bank, 4096, filters_per_lane=8)["lanes_per_group"] == 256

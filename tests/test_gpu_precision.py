@@ -8,9 +8,9 @@ lane holds one filter (no in-lane sum), the 256 filters of each workgroup are
 coherent (b0 of one sign, zero delay), so the partial sums inside a piece grow
 to hundreds of times a single output, and the two workgroups' pieces cancel
 to about 1%.  The plain sum's roundings are then relative to the large
-partial sums; the compensated sum (error-free cross-lane levels) leaves only
-the products' and the piece totals' roundings, and must be measurably closer
-to the FP64 oracle."""
+partial sums; the compensated sum (cross-lane levels accumulated in FP64)
+leaves only the products' and the run and piece totals' roundings, and must be
+measurably closer to the FP64 oracle."""
 import numpy as np
 import pytest
 
