@@ -219,8 +219,18 @@ def serving_bench(args, S, W, torch, np):
     max_block = 8192
     prec = args.precision
     stream = torch.cuda.Stream()
+    # A batched launch covers every bank of the batch at once, so its banks take
+    # the shape of a bank that fills the device (4 filters per lane, 8 waves);
+    # the plain policy launches each bank alone and keeps the library's default
+    # for the bank's size (4-wave groups for banks of under about 4 rounds of
+    # workgroups).  An explicit --filters-per-lane / --waves-per-group is used for
+    # both.
     shape = dict(filters_per_lane=args.filters_per_lane, waves_per_group=args.waves_per_group)
-    base = [S.Bank(t, max_block, stream=stream, precision=prec, workspace=S.WORKSPACE_CALLER, **shape)
+    if not (args.filters_per_lane or args.waves_per_group):
+        shape_b = dict(filters_per_lane=4, waves_per_group=8)
+    else:
+        shape_b = shape
+    base = [S.Bank(t, max_block, stream=stream, precision=prec, workspace=S.WORKSPACE_CALLER, **shape_b)
             for t in tables]
     print(f"serving: {total_t} templates in {len(base)} banks created", file=sys.stderr, flush=True)
     ws_bytes = max(b.workspace_bytes for b in base)
@@ -316,7 +326,7 @@ def serving_bench(args, S, W, torch, np):
     # ---- 2. real-time capacity
     if args.serve_seconds > 0:
         out["serving"] = serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_bytes,
-                                          fs_step, value, max_block, prec)
+                                          fs_step, value, max_block, prec, shape, shape_b, stream)
         cap = out["serving"]
         out["real_time_templates"] = cap["real_time_templates"]
         out["real_time_templates_plain"] = cap["real_time_templates_plain"]
@@ -330,16 +340,35 @@ def serving_bench(args, S, W, torch, np):
 
 
 def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_bytes, fs_step, sat_value,
-                     max_block, prec):
+                     max_block, prec, shape, shape_b, stream):
     """Largest resident template count (in copies of the stream banks) that the
     continuous-batching scheduler serves at real-time Poisson arrivals, and the
     plain form at the same count and at its own largest sustained count."""
     n_streams = 1 + max(streams_of)
     per_set = sum(t.n_templates for t in tables)
     rate = 4096
-    bank_pool = {id(t): [b] for t, b in zip(tables, base)}
-    be_kw = dict(precision=prec, workspace=S.WORKSPACE_CALLER, filters_per_lane=args.filters_per_lane,
-                 waves_per_group=args.waves_per_group)
+    kw = dict(precision=prec, workspace=S.WORKSPACE_CALLER)
+    be_kw = {"batched": dict(kw, **shape_b), "plain": dict(kw, **shape)}
+    # the plain policy's banks: the same as the batched ones where the
+    # library's default shape for the bank is the batched shape
+    base_p = []
+    for t, b in zip(tables, base):
+        p = S.spiir_plan(t, max_block, **be_kw["plain"])
+        same = (p["filters_per_lane"], p["lanes_per_group"]) == (b.plan["filters_per_lane"], b.plan["lanes_per_group"])
+        base_p.append(b if same else S.Bank(t, max_block, stream=stream, **be_kw["plain"]))
+    extra = [b for b in base_p if all(b is not c for c in base)]
+    ws_bytes = max([ws_bytes] + [b.workspace_bytes for b in extra])
+    pool_b = {id(t): [b] for t, b in zip(tables, base)}
+    bank_pool = {"batched": pool_b, "plain": pool_b if not extra else {id(t): [b] for t, b in zip(tables, base_p)}}
+
+    def free_pool(pool, keep):
+        """Destroys the copies a pool gathered, keeping the banks in `keep`."""
+        for lst in pool.values():
+            for b in lst:
+                if all(b is not c for c in keep):
+                    b.destroy()
+            lst[:] = [b for b in lst if any(b is c for c in keep)]
+        torch.cuda.synchronize()
     dur = args.serve_seconds
     arr = W.serving_arrivals(5005, n_streams, dur, rate_hz=rate, speed=1.0)
     # Poisson arrival times scaled per stream so that its last block arrives
@@ -348,12 +377,12 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
     arr = [(l, t * (l.sum() / rate) / t[-1]) for l, t in arr]
     xs = [W.noise_stream(2100 + s, int(l.sum())) for s, (l, _) in enumerate(arr)]
 
-    def backend():
+    def backend(policy):
         return SV.HipBackend(xs, n_streams=2, pool_templates=max(t.n_templates for t in tables),
-                             pool_workspace=ws_bytes, max_block=max_block, bank_pool=bank_pool,
-                             return_to_pool=True, **be_kw)
+                             pool_workspace=ws_bytes, max_block=max_block, bank_pool=bank_pool[policy],
+                             return_to_pool=True, **be_kw[policy])
 
-    fp_set = sum(S.spiir_footprint(t, max_block, **be_kw) for t in tables)
+    fp_set = max(sum(S.spiir_footprint(t, max_block, **be_kw[pol]) for t in tables) for pol in be_kw)
     pool_bytes = (2 * 16 * (max(t.n_templates for t in tables) * max_block * 8 + ws_bytes))
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -371,7 +400,7 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
 
     def trial(policy, k):
         units = [(streams_of[b], tables[b]) for _ in range(k) for b in range(len(tables))]
-        be = backend()
+        be = backend(policy)
         sch = SV.Scheduler(be, units=units, max_block=max_block, hbm_budget=budget, policy=policy,
                            abort_backlog_s=args.serve_backlog_s, max_inflight=args.serve_inflight,
                            merge_max=args.serve_merge_max)
@@ -420,8 +449,12 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
         return best, runs
 
     k_b, runs_b = search("batched", int(round(k_est)))
+    if extra:  # the plain policy's own banks: the batched copies make room for them
+        free_pool(bank_pool["batched"], base)
     plain_same = trial("plain", k_b) if k_b > 0 else None
     k_p, runs_p = search("plain", k_b, first=plain_same) if plain_same is not None else (0, [])
+    free_pool(bank_pool["plain"], base)
+    free_pool(bank_pool["batched"], base)
     best_b = next((r for r in runs_b if r["copies"] == k_b), None)
     best_p = next((r for r in runs_p if r["copies"] == k_p), None)
     keys = ("copies", "templates", "sustained", "aborted", "p50_ms", "p99_ms", "max_ms", "drain_s",
@@ -444,6 +477,9 @@ def serving_capacity(args, S, W, SV, torch, np, tables, streams_of, base, ws_byt
                        f"(oldest unfinished block) stays under {args.serve_backlog_s:g} s and it ends "
                        f"within {args.serve_drain_s:g} s of the last arrival"),
         "output": "z written to pooled buffers (one per device stream and batch slot)",
+        "bank_shapes": {pol: {"filters_per_lane": b.plan["filters_per_lane"],
+                              "lanes_per_group": b.plan["lanes_per_group"]}
+                        for pol, b in (("batched", base[0]), ("plain", base_p[0]))},
     }
 
 
