@@ -226,10 +226,7 @@ def serving_bench(args, S, W, torch, np):
     # workgroups).  An explicit --filters-per-lane / --waves-per-group is used for
     # both.
     shape = dict(filters_per_lane=args.filters_per_lane, waves_per_group=args.waves_per_group)
-    if not (args.filters_per_lane or args.waves_per_group):
-        shape_b = dict(filters_per_lane=4, waves_per_group=8)
-    else:
-        shape_b = shape
+    shape_b = shape if (args.filters_per_lane or args.waves_per_group) else dict(SV.BATCHED_BANK_SHAPE)
     base = [S.Bank(t, max_block, stream=stream, precision=prec, workspace=S.WORKSPACE_CALLER, **shape_b)
             for t in tables]
     print(f"serving: {total_t} templates in {len(base)} banks created", file=sys.stderr, flush=True)

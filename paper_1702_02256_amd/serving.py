@@ -36,6 +36,14 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+# Launch shape for banks served by the batched policy: a batched launch covers
+# every bank of the batch at once, so its banks take the shape of a bank that
+# fills the device (4 filters per lane, 8 waves per group) even when each bank
+# alone would get the library's smaller default (4-wave groups for banks of
+# under about 4 rounds of workgroups).  Pass it in ``bank_kw`` of HipBackend;
+# the plain policy keeps the per-bank default.
+BATCHED_BANK_SHAPE = {"filters_per_lane": 4, "waves_per_group": 8}
+
 
 @dataclass
 class Block:

@@ -219,3 +219,18 @@ def test_backlog_counts_only_unfinished_blocks_with_two_batches_in_flight():
     summ = st.summary()
     assert not st.aborted, summ
     assert summ["blocks"] == summ["blocks_arrived"]
+
+
+def test_batched_bank_shape_is_the_full_device_default():
+    # the shape the batched policy gives every bank is the one the library
+    # picks by itself for a bank that fills the device; a small bank alone
+    # gets 4-wave groups unless it is given that shape
+    from paper_1702_02256_amd import spiir as S
+    want = (SV.BATCHED_BANK_SHAPE["filters_per_lane"], 64 * SV.BATCHED_BANK_SHAPE["waves_per_group"])
+    for prec in ("fp32", "fp32_compensated"):
+        p = S.spiir_plan(W.config3(n_blocks=1).bank, 4096, precision=prec)
+        assert (p["filters_per_lane"], p["lanes_per_group"]) == want, prec
+    small = W.config3(n_templates=1024, n_blocks=1).bank
+    assert S.spiir_plan(small, 4096)["lanes_per_group"] == 256
+    p = S.spiir_plan(small, 4096, **SV.BATCHED_BANK_SHAPE)
+    assert (p["filters_per_lane"], p["lanes_per_group"]) == want
