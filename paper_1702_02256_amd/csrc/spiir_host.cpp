@@ -268,14 +268,17 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub, int copie
     // plus a term common to all lanes.  64-bit reads are served 32 lanes at a
     // time over 64 banks, so within one half-wave and slot the lanes conflict
     // exactly when their classes agree.  With one copy the tile reads the
-    // words x[k - d] and x[k + 1 - d] (banks (-d) mod 64 and the next, plus the
-    // common term, 32 lanes at a time): lanes in distinct classes never share
-    // a bank there either, so the same placement serves both layouts and the
-    // summation order, hence the output, does not depend on the layout.  Each
-    // segment's filters are dealt to its (lane, slot) positions greedily,
-    // picking for every position a class that is least used so far in that row.
+    // words x[k - d] and x[k + 1 - d] as two 32-bit accesses, served 32 lanes
+    // at a time over 32 banks: there the class is (-d) mod 32 (two-copy
+    // classes c and c + 16 of one parity would share a bank).  The two layouts
+    // therefore place a bank's filters differently, and their outputs differ by
+    // the order of the sum.  Each segment's filters are dealt to its (lane,
+    // slot) positions greedily, picking for every position a class that is
+    // least used so far in that row.
     constexpr int kBanks = 32;
-    auto bank_class = [](int dj) { return (15 * (dj & 1) - (dj >> 1)) & (kBanks - 1); };
+    auto bank_class = [copies](int dj) {
+        return copies == 2 ? (15 * (dj & 1) - (dj >> 1)) & (kBanks - 1) : (-dj) & (kBanks - 1);
+    };
     const int halves = L / 32;
     using Counts = std::vector<uint16_t>;  // [F][halves][kBanks]
     auto fresh_counts = [&]() { return Counts((size_t)F * halves * kBanks, 0); };

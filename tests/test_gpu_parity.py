@@ -415,20 +415,29 @@ def test_carry_chunk_variants(C):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp32_compensated"])
-def test_one_window_copy_gives_the_same_bits(precision):
+def test_one_and_two_window_copies(precision):
     """The single-copy input window (two 32-bit reads per sample pair) reads the same
-    samples as the two-copy one, so the output is identical; checked on a
-    multi-rate bank and a single-rate bank with long delays."""
+    samples as the two-copy one; the two layouts place the filters by different
+    LDS bank classes, so they sum in different orders: each meets the bar
+    against the oracle, and they agree with each other to within FP32 summation
+    rounding.  Checked on a multi-rate bank and a single-rate bank with long
+    delays."""
     tb_mr = _mr_bank(seed=61, T=5, H=4, rate=2048)
     tb_sr = W.random_bank(62, np.array([[300], [41], [180]], np.int32), 2048, [4095])
     x = W.noise_stream(63, 4 * 2048)
     for tb in (tb_mr, tb_sr):
+        zr = oracle.run_stream(tb, x)
         z1 = run_gpu(tb, x, [2048, 1000, 1048, 4096], max_block=4096, precision=precision,
                      window_copies=1)
         z2 = run_gpu(tb, x, [2048, 1000, 1048, 4096], max_block=4096, precision=precision,
                      window_copies=2)
-        assert np.array_equal(z1, z2)
-        check(z1, oracle.run_stream(tb, x), label=f"one window copy ({precision})")
+        check(z1, zr, label=f"one window copy ({precision})")
+        check(z2, zr, label=f"two window copies ({precision})")
+        d = np.max(np.abs(z1 - z2), axis=1) / np.max(np.abs(zr), axis=1)
+        _say(f"one against two window copies ({precision}): max rel difference {d.max():.3e}")
+        # the filters' recurrences are the same arithmetic in both layouts; only
+        # the order of the FP32 sum over a few hundred partials differs
+        assert d.max() < 2e-6, d.max()
 
 
 def test_compensated_mode():
