@@ -272,9 +272,14 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub, int copie
     // at a time over 32 banks: there the class is (-d) mod 32 (two-copy
     // classes c and c + 16 of one parity would share a bank).  The two layouts
     // therefore place a bank's filters differently, and their outputs differ by
-    // the order of the sum.  Each segment's filters are dealt to its (lane,
-    // slot) positions greedily, picking for every position a class that is
-    // least used so far in that row.
+    // the order of the sum.  A segment's filters go to the (slot, half-wave)
+    // rows of its lanes class by class, the classes with most filters first,
+    // each filter to the row that holds fewest of its class so far (counting
+    // the other segments sharing the row), ties to the row with most room.  A
+    // segment's classes are uneven, so some rows must hold a class twice; this
+    // order spreads the frequent classes before the rows fill (per filter slot
+    // in lane order, least-used class first, left about 10% more conflict
+    // cycles).
     constexpr int kBanks = 32;
     auto bank_class = [copies](int dj) {
         return copies == 2 ? (15 * (dj & 1) - (dj >> 1)) & (kBanks - 1) : (-dj) & (kBanks - 1);
@@ -327,18 +332,59 @@ int make_plan_shape(const spiir_bank_desc* d, Plan& p, int W, int sub, int copie
                 bucket[bank_class(dj)].push_back(j);
             }
             std::vector<int> assign((size_t)nl * F, -1);
-            for (int f = 0; f < F; ++f)
-                for (int i = 0; i < nl; ++i) {
-                    if (i * F + f >= M) continue;  // padding positions: the tail of the last lane
-                    uint16_t* row = counts[lane_wg[i]].data() +
-                                    ((size_t)f * halves + lane_pos[i] / 32) * kBanks;
-                    int best = -1;
-                    for (int r = 0; r < kBanks; ++r)
-                        if (!bucket[r].empty() && (best < 0 || row[r] < row[best])) best = r;
-                    assign[(size_t)i * F + f] = bucket[best].back();
-                    bucket[best].pop_back();
-                    row[best]++;
-                }
+            {
+                // cells: (slot, half-wave row) of the segment's positions, each
+                // with its positions in lane order
+                struct Cell {
+                    uint16_t* row;
+                    std::vector<int> pos;  // i * F + f
+                    int used = 0;
+                };
+                std::vector<Cell> cells;
+                std::vector<int> cell_of_key;
+                auto key_of = [&](int i, int f) {
+                    return ((lane_wg[i] * F + f) * halves) + lane_pos[i] / 32;
+                };
+                int max_key = 0;
+                for (int i = 0; i < nl; ++i)
+                    for (int f = 0; f < F; ++f) max_key = std::max(max_key, key_of(i, f));
+                cell_of_key.assign((size_t)max_key + 1, -1);
+                for (int f = 0; f < F; ++f)
+                    for (int i = 0; i < nl; ++i) {
+                        if (i * F + f >= M) continue;  // padding positions: the tail of the last lane
+                        const int k = key_of(i, f);
+                        if (cell_of_key[k] < 0) {
+                            cell_of_key[k] = (int)cells.size();
+                            Cell c;
+                            c.row = counts[lane_wg[i]].data() + ((size_t)f * halves + lane_pos[i] / 32) * kBanks;
+                            cells.push_back(std::move(c));
+                        }
+                        cells[cell_of_key[k]].pos.push_back(i * F + f);
+                    }
+                // classes with the most filters first; each filter to the cell
+                // holding fewest of its class so far, then the one with most room
+                std::vector<int> order(kBanks);
+                for (int r = 0; r < kBanks; ++r) order[r] = r;
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](int a, int b) { return bucket[a].size() > bucket[b].size(); });
+                for (int r : order)
+                    while (!bucket[r].empty()) {
+                        int best = -1;
+                        for (int c = 0; c < (int)cells.size(); ++c) {
+                            const Cell& C = cells[c];
+                            const int room = (int)C.pos.size() - C.used;
+                            if (room == 0) continue;
+                            if (best < 0) { best = c; continue; }
+                            const Cell& B = cells[best];
+                            const int broom = (int)B.pos.size() - B.used;
+                            if (C.row[r] < B.row[r] || (C.row[r] == B.row[r] && room > broom)) best = c;
+                        }
+                        Cell& C = cells[best];
+                        assign[(size_t)C.pos[C.used++]] = bucket[r].back();
+                        bucket[r].pop_back();
+                        C.row[r]++;
+                    }
+            }
 
             SegDesc& sg = p.seg[(size_t)t * H + h];
             sg.zoff = p.zw_elems;

@@ -5,7 +5,8 @@ On the multi-rate workloads the FP32 recurrence sets the error (about 2e-6 of
 max |z| either way), so compensating the sum changes nothing measurable.  Here
 the recurrence is one rounded product per filter (a1 = 0, no memory), each
 lane holds one filter (no in-lane sum), the 256 filters of each workgroup are
-coherent (b0 of one sign, zero delay), so the partial sums inside a piece grow
+coherent (b0 of one sign, zero delay; the signs follow the planner's placement
+of a single delay class), so the partial sums inside a piece grow
 to hundreds of times a single output, and the two workgroups' pieces cancel
 to about 1%.  The plain sum's roundings are then relative to the large
 partial sums; the compensated sum (cross-lane levels accumulated in FP64)
@@ -40,7 +41,14 @@ def test_compensated_sum_beats_plain_where_the_sum_dominates():
     rng = np.random.default_rng(808)
     pos = rng.uniform(0.5, 1.5, 256) + 1j * rng.uniform(0.5, 1.5, 256)
     neg = -pos * (1.0 + 0.02 * rng.uniform(0.0, 1.0, 256))
-    b0 = np.concatenate([pos, neg])
+    # With one delay class the planner deals filter j to half-wave row j mod 16
+    # of the template's 512 lanes (rows 0-7 are the first workgroup, 8-15 the
+    # second), so the filters with j mod 16 < 8 form the first workgroup's piece
+    # and the others the second's.
+    first = (np.arange(512) % 16) < 8
+    b0 = np.empty(512, np.complex128)
+    b0[first] = pos
+    b0[~first] = neg
     M = len(b0)
     tb = W.BankTables(4096, np.array([[M]], np.int32), np.zeros(M, np.complex128), b0,
                       np.zeros(M, np.int32))
