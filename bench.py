@@ -503,12 +503,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=50,
                     help="untimed blocks first; the clocks settle after about 30")
     ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5])
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="config 5: seconds of data per stream in each real-time capacity run "
                          "(0 = saturated step only)")
     ap.add_argument("--serve-backlog-s", type=float, default=5.0,
                     help="config 5: a capacity run stops once its oldest unfinished block is this old")
-    ap.add_argument("--serve-drain-s", type=float, default=0.5,
+    ap.add_argument("--serve-drain-s", type=float, default=1.0,
                     help="config 5: a capacity run keeps up if it ends within this long after "
                          "the last arrival")
     ap.add_argument("--serve-inflight", type=int, default=2,
