@@ -124,7 +124,10 @@ enum {
  *                         a sample pair with one aligned 64-bit access) or as
  *                         one (two 32-bit accesses, half the LDS, so long
  *                         delay windows leave room for more workgroups per
- *                         compute unit).  Results do not depend on it.
+ *                         compute unit).  The two layouts place the filters
+ *                         on lanes by different LDS bank classes, so their
+ *                         results differ by the order of the FP32 sum over
+ *                         filters only.
  *   workspace             SPIIR_WORKSPACE_OWN (0): spiir_create allocates the
  *                         bank's workspace (the per-piece band outputs that
  *                         the filter kernel hands to the upsample-and-add
